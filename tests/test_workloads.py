@@ -1,0 +1,61 @@
+"""Checks of the seeded input generators (shapes, IDs, flags, determinism)."""
+import numpy as np
+
+from paper_2110_01716_amd import workloads as wl
+
+
+def test_box_mesh_counts_and_ids():
+    m = wl.box_mesh(4, N=7)
+    assert m.x.shape == (64, 512) and m.gid.dtype == np.int64
+    assert len(np.unique(m.gid)) == 29 ** 3
+    # interior unique nodes
+    ids, first = np.unique(m.gid.ravel(), return_index=True)
+    assert np.sum(m.dirichlet.ravel()[first] == 0) == 27 ** 3
+    # copies of a node share coordinates bitwise
+    for c in (m.x, m.y, m.z):
+        _, inv = np.unique(m.gid.ravel(), return_inverse=True)
+        mn = np.full(len(ids), np.inf)
+        mx = np.full(len(ids), -np.inf)
+        np.minimum.at(mn, inv, c.ravel())
+        np.maximum.at(mx, inv, c.ravel())
+        assert np.all(mn == mx)
+
+
+def test_deformed_mesh_consistent_and_seeded():
+    a = wl.box_mesh(3, N=5, deform=0.05, seed=4)
+    b = wl.box_mesh(3, N=5, deform=0.05, seed=4)
+    c = wl.box_mesh(3, N=5, deform=0.05, seed=5)
+    assert np.array_equal(a.x, b.x) and not np.array_equal(a.x, c.x)
+    ids, inv = np.unique(a.gid.ravel(), return_inverse=True)
+    mn = np.full(len(ids), np.inf)
+    mx = np.full(len(ids), -np.inf)
+    np.minimum.at(mn, inv, a.y.ravel())
+    np.maximum.at(mx, inv, a.y.ravel())
+    assert np.all(mn == mx)
+
+
+def test_random_rhs_consistent_masked():
+    m = wl.box_mesh(3, N=3, deform=0.05, seed=1)
+    b = wl.random_rhs(m, 7)
+    assert np.all(b[m.dirichlet != 0] == 0)
+    assert np.all(np.abs(b) <= 1)
+    _, inv = np.unique(m.gid.ravel(), return_inverse=True)
+    s = np.zeros(inv.max() + 1)
+    np.maximum.at(s, inv, b.ravel())
+    assert np.allclose(s[inv], np.maximum(b.ravel(), s[inv]))
+    assert np.array_equal(b, wl.random_rhs(m, 7))
+
+
+def test_relabel_preserves_structure():
+    m = wl.box_mesh(2, N=3)
+    r = wl.relabel(m, 3)
+    assert np.array_equal(r.x, m.x[r.meta["perm"]])
+    assert len(np.unique(r.gid)) == len(np.unique(m.gid))
+
+
+def test_named_workloads():
+    cfg = wl.config_meshes()
+    assert cfg["ax_64x64x64_N7"]["n"] == 64
+    specs = wl.batched_problem_specs()
+    assert len(specs) == 256 and {s["N"] for s in specs} == {5, 7, 9}
+    assert wl.serving_mesh_sides() == [8, 10, 12, 14, 17, 19, 21, 23, 25, 27, 29, 31, 34, 36, 38, 40]
