@@ -1,0 +1,1053 @@
+// Solver engine: Jacobi-PCG and pMG-preconditioned flexible CG for one or
+// many independent problems.
+//
+// Paper: the pressure solve runs flexible CG (a short recurrence tolerant of
+// the nonsymmetric pMG preconditioner, Implementation, FlexCG/GMRES paragraph)
+// around a p-multigrid V-cycle whose smoothers are Chebyshev-accelerated point
+// Jacobi, all pMG steps in 32-bit (Implementation, pMG paragraph); the coarse
+// level is solved approximately (the paper uses AMG on the CPU; here FP64
+// Jacobi-PCG to a loose tolerance on the GPU). Velocity-type solves use
+// Jacobi-PCG (Implementation, Helmholtz paragraph).
+//
+// Execution model:
+//   * every solve occupies a Slot: its workspace vectors, partial-sum buffer and
+//     a block of device scalars/flags (alpha, beta, norms, done, status, iters);
+//   * an iteration is a fixed sequence of phases (Ax, gs, fused vector updates,
+//     finalize reductions, transfers); each phase is ONE launch covering every
+//     active slot of a group (per-problem argument tables, block offsets);
+//   * all scalar recurrences stay on the device; the host only polls done
+//     flags (every check_every outer iterations, every coarse_check_every
+//     coarse iterations); finished problems skip via their flags, so a
+//     problem's arithmetic never depends on the other problems in the batch;
+//   * reductions are per block in a fixed order, then per problem in a fixed
+//     order: a solve gives bitwise the same result alone or in any mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <type_traits>
+
+#include "sem_internal.h"
+
+namespace sem {
+
+using Fn = std::function<void(hipStream_t)>;
+using Clock = std::chrono::steady_clock;
+
+// ---------------------------------------------------------------------------
+// workspace pool: reuse freed solve workspaces (no allocation on the hot path)
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_pool_mu;
+std::multimap<size_t, void*> g_pool;
+
+void* pool_get(size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pool.lower_bound(bytes);
+    if (it != g_pool.end() && it->first <= bytes + bytes / 8) {
+      void* p = it->second;
+      g_pool.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto& kv : g_pool) (void)hipFree(kv.second);
+    g_pool.clear();
+    e = hipMalloc(&p, bytes);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(e == hipErrorOutOfMemory ? SEM_ENOMEM : SEM_EHIP, "workspace allocation of %zu bytes failed: %s", bytes,
+         hipGetErrorString(e));
+  }
+  return p;
+}
+
+void pool_put(void* p, size_t bytes) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pool.emplace(bytes, p);
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// slots
+// ---------------------------------------------------------------------------
+struct Slot {
+  sem_mesh_s* mesh = nullptr;
+  sem_pmg_s* pmg = nullptr;
+  const double* b = nullptr;
+  double* x = nullptr;
+  sem_solve_opts o{};
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *w = nullptr;
+  void *lr[kMaxLevels] = {}, *lx[kMaxLevels] = {}, *lres[kMaxLevels] = {}, *ld[kMaxLevels] = {},
+       *lt[kMaxLevels] = {};
+  double *cr = nullptr, *cx = nullptr, *cp = nullptr, *cw = nullptr;
+  double* partial = nullptr;
+  int64_t stride = 0;
+  int idx = -1;
+  int state = 0;  // 0 free, 1 admitted, 2 running, 3 finished
+  Clock::time_point t0;
+  sem_solve_info info{};
+  double* scal[2] = {nullptr, nullptr};  // device: outer, coarse
+  int* flags[2] = {nullptr, nullptr};
+
+  const MeshData& level(int l) const { return pmg ? pmg->lv[l].mesh->d : mesh->d; }
+  int nlev() const { return pmg ? pmg->n_levels : 1; }
+  bool f32() const { return pmg && pmg->o.smoother_dtype == SEM_F32; }
+};
+
+namespace {
+
+size_t align_up(size_t n) { return (n + 255) & ~size_t(255); }
+
+// layout of a slot workspace; with base == nullptr only computes the size
+size_t layout(Slot& s, uint8_t* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  const MeshData& f = s.level(0);
+  const int64_t n0 = f.nloc;
+  int64_t stride = std::max<int64_t>(ax_blocks(f.N, f.E), vec_blocks(n0));
+  s.r = (double*)take(8 * n0);
+  s.z = (double*)take(8 * n0);
+  s.p = (double*)take(8 * n0);
+  s.w = (double*)take(8 * n0);
+  if (s.pmg) {
+    const int L = s.pmg->n_levels;
+    const size_t ts = s.f32() ? 4 : 8;
+    for (int l = 0; l + 1 < L; ++l) {
+      const int64_t nl = s.level(l).nloc;
+      s.lr[l] = take(ts * nl);
+      s.lx[l] = take(ts * nl);
+      s.lres[l] = take(ts * nl);
+      s.ld[l] = take(ts * nl);
+      s.lt[l] = take(ts * nl);
+    }
+    const MeshData& c = s.level(L - 1);
+    s.cr = (double*)take(8 * c.nloc);
+    s.cx = (double*)take(8 * c.nloc);
+    s.cp = (double*)take(8 * c.nloc);
+    s.cw = (double*)take(8 * c.nloc);
+    stride = std::max<int64_t>(stride, std::max<int64_t>(ax_blocks(c.N, c.E), vec_blocks(c.nloc)));
+  }
+  s.stride = stride;
+  s.partial = (double*)take(8 * 2 * stride);
+  return off;
+}
+
+template <typename T>
+const T* G_of(const MeshData& m) {
+  if constexpr (sizeof(T) == 8) return m.G64.as<double>(); else return m.G32.as<float>();
+}
+template <typename T>
+const T* D_of(const MeshData& m) {
+  if constexpr (sizeof(T) == 8) return m.Dg64.as<double>(); else return m.Dg32.as<float>();
+}
+template <typename T>
+const T* dinv_of(const MeshData& m) {
+  if constexpr (sizeof(T) == 8) return m.dinv64.as<double>(); else return m.dinv32.as<float>();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plans: launch sequences over a set of slots
+// ---------------------------------------------------------------------------
+struct Group {
+  std::vector<Slot*> S;
+  bool pmg = false;
+  bool vcycle_only = false;
+  int L = 1;
+  std::vector<Fn> init, head, cinit, citer, tail;
+  int coarse_limit = 0, coarse_fixed = 0, coarse_check = 8;
+};
+
+class Plan {
+ public:
+  std::vector<uint8_t> host;
+  DevBuf dev;
+  std::vector<Group> groups;
+
+  size_t push(const void* p, size_t n) {
+    const size_t off = align_up(host.size());
+    host.resize(off + n);
+    std::memcpy(host.data() + off, p, n);
+    return off;
+  }
+  const uint8_t* base() const { return dev.as<uint8_t>(); }
+
+  void upload(hipStream_t s) {
+    if (host.empty()) return;
+    dev.alloc(host.size());
+    SEM_HIP(hipMemcpyAsync(dev.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  }
+
+  template <typename A, typename L>
+  void add(std::vector<Fn>& seq, const std::vector<A>& args, const std::vector<int>& starts, L launch) {
+    const int n = (int)args.size();
+    if (n == 0) return;
+    if (n == 1) {
+      A one = args[0];
+      seq.push_back([one, launch](hipStream_t s) {
+        Table<A> t;
+        t.one = one;
+        launch(t, s);
+      });
+      return;
+    }
+    const size_t oa = push(args.data(), sizeof(A) * n);
+    const size_t os = push(starts.data(), sizeof(int) * (n + 1));
+    seq.push_back([this, oa, os, n, launch](hipStream_t s) {
+      Table<A> t;
+      t.many = reinterpret_cast<const A*>(base() + oa);
+      t.starts = reinterpret_cast<const int*>(base() + os);
+      t.n = n;
+      launch(t, s);
+    });
+  }
+
+  // A(u -> t) at level l: local Ax (optionally with the fused u.Au partial) then gs + mask
+  template <typename T, typename FU, typename FT>
+  void apply_A(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, FU u_of, FT t_of, bool with_partial,
+               int skip_mode) {
+    std::map<int, std::vector<Slot*>> by;
+    for (Slot* s : S) by[s->level(l).N].push_back(s);
+    for (auto& kv : by) {
+      const int N = kv.first;
+      std::vector<AxArgs<T>> args;
+      std::vector<int> starts{0};
+      for (Slot* s : kv.second) {
+        const MeshData& m = s->level(l);
+        AxArgs<T> a;
+        a.G = G_of<T>(m);
+        a.u = u_of(*s);
+        a.Au = t_of(*s);
+        a.e0 = 0;
+        a.ne = m.E;
+        a.partial = with_partial ? s->partial : nullptr;
+        a.skip = skip(*s, skip_mode);
+        args.push_back(a);
+        starts.push_back(starts.back() + ax_blocks(N, m.E));
+      }
+      const T* D = D_of<T>(kv.second[0]->level(l));
+      const int64_t total = starts.back();
+      add(seq, args, starts, [N, D, total](const Table<AxArgs<T>>& t, hipStream_t st) {
+        launch_ax<T>(N, t, total, D, st);
+      });
+    }
+    gs<T>(seq, S, l, t_of, skip_mode);
+  }
+
+  template <typename T, typename FV>
+  void gs(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, FV v_of, int skip_mode) {
+    std::vector<GsArgs<T>> args;
+    std::vector<int> starts{0};
+    for (Slot* s : S) {
+      const MeshData& m = s->level(l);
+      GsArgs<T> a;
+      a.v = v_of(*s);
+      a.off = m.gs_off.as<int>();
+      a.idx = m.gs_idx.as<int>();
+      a.sdir = m.gs_dir.as<uint8_t>();
+      a.dir_idx = m.dir_idx.as<int>();
+      a.n_shared = m.n_shared;
+      a.n_dir = m.n_dir_single;
+      a.mask = 1;
+      a.skip = skip(*s, skip_mode);
+      args.push_back(a);
+      starts.push_back(starts.back() + (int)gs_blocks(m.n_shared, m.n_dir_single));
+    }
+    const int64_t total = starts.back();
+    add(seq, args, starts, [total](const Table<GsArgs<T>>& t, hipStream_t st) { launch_gs<T>(t, total, st); });
+  }
+
+  template <typename T, typename F>
+  void vec(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, VecOp op, F fill, int skip_mode) {
+    std::vector<VecArgs<T>> args;
+    std::vector<int> starts{0};
+    for (Slot* s : S) {
+      const MeshData& m = s->level(l);
+      VecArgs<T> a;
+      a.n = m.nloc;
+      a.owner = m.owner.as<uint8_t>();
+      a.partial = s->partial;
+      a.stride = s->stride;
+      a.skip = skip(*s, skip_mode);
+      fill(*s, a);
+      args.push_back(a);
+      starts.push_back(starts.back() + (int)vec_blocks(m.nloc));
+    }
+    const int64_t total = starts.back();
+    add(seq, args, starts, [op, total](const Table<VecArgs<T>>& t, hipStream_t st) { launch_vec<T>(op, t, total, st); });
+  }
+
+  template <typename Tin, typename Tout, typename F>
+  void cast(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, F fill, int skip_mode) {
+    std::vector<CastArgs<Tin, Tout>> args;
+    std::vector<int> starts{0};
+    for (Slot* s : S) {
+      CastArgs<Tin, Tout> a;
+      a.n = s->level(l).nloc;
+      a.skip = skip(*s, skip_mode);
+      fill(*s, a);
+      args.push_back(a);
+      starts.push_back(starts.back() + (int)vec_blocks(a.n));
+    }
+    const int64_t total = starts.back();
+    add(seq, args, starts, [total](const Table<CastArgs<Tin, Tout>>& t, hipStream_t st) {
+      launch_cast<Tin, Tout>(t, total, st);
+    });
+  }
+
+  // stage 0 = outer, 1 = coarse; nblk from the producing kernel's blocks
+  template <typename F>
+  void fin(std::vector<Fn>& seq, const std::vector<Slot*>& S, FinOp op, int stage, F nblk_of, int skip_mode,
+           double rtol = 0, int maxit = 0, int fixed = 0, bool count_total = false) {
+    std::vector<FinArgs> args;
+    std::vector<int> starts{0};
+    for (Slot* s : S) {
+      FinArgs a;
+      a.partial = s->partial;
+      a.stride = s->stride;
+      a.nblk = nblk_of(*s);
+      a.scal = s->scal[stage];
+      a.flags = s->flags[stage];
+      a.rtol = rtol;
+      a.maxit = maxit;
+      a.fixed = fixed;
+      a.total = count_total ? s->flags[0] + F_TOTAL : nullptr;
+      a.skip = skip(*s, skip_mode);
+      if (stage == 0) {
+        a.rtol = s->o.rtol;
+        a.maxit = s->o.maxit;
+        a.fixed = s->o.fixed_iters;
+      }
+      args.push_back(a);
+      starts.push_back(starts.back() + 1);
+    }
+    const int n = (int)args.size();
+    add(seq, args, starts, [op, n](const Table<FinArgs>& t, hipStream_t st) { launch_fin(op, t, n, st); });
+  }
+
+  template <typename Tf, typename Tc, typename F>
+  void xfer(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, int dir, F fill, int skip_mode) {
+    std::map<std::pair<int, int>, std::vector<Slot*>> by;
+    for (Slot* s : S) by[{s->level(l).N, s->level(l + 1).N}].push_back(s);
+    for (auto& kv : by) {
+      const int Nf = kv.first.first, Nc = kv.first.second;
+      std::vector<XferArgs<Tf, Tc>> args;
+      std::vector<int> starts{0};
+      for (Slot* s : kv.second) {
+        XferArgs<Tf, Tc> a;
+        a.E = s->level(l).E;
+        a.skip = skip(*s, skip_mode);
+        fill(*s, a);
+        args.push_back(a);
+        starts.push_back(starts.back() + xfer_blocks(Nf, Nc, a.E));
+      }
+      const PmgLevel& lv = kv.second[0]->pmg->lv[l];
+      const double* M = dir == 0 ? lv.J.as<double>() : lv.JT.as<double>();
+      const int64_t total = starts.back();
+      add(seq, args, starts, [dir, Nf, Nc, total, M](const Table<XferArgs<Tf, Tc>>& t, hipStream_t st) {
+        launch_xfer<Tf, Tc>(dir, Nf, Nc, t, total, M, st);
+      });
+    }
+  }
+
+  // skip modes: 0 none, 1 outer done, 2 outer or coarse done
+  static Skip skip(const Slot& s, int mode) {
+    Skip k;
+    if (mode >= 1) k.f0 = s.flags[0] + F_DONE;
+    if (mode >= 2) k.f1 = s.flags[1] + F_DONE;
+    return k;
+  }
+
+  template <typename T>
+  void build_vcycle(Group& g);
+  void build_flex(Group& g);
+  void build_jacobi(Group& g);
+  void build_init(Group& g);
+};
+
+// ---------------------------------------------------------------------------
+// V-cycle: r (FP64, slot.r) -> z (FP64, slot.z)
+// ---------------------------------------------------------------------------
+template <typename T>
+void Plan::build_vcycle(Group& g) {
+  auto& S = g.S;
+  const int L = g.L;
+  const sem_pmg_opts& o = S[0]->pmg->o;
+  const int K = o.cheb_degree;
+  constexpr int SK = 1;  // skip when the outer solve is done
+
+  if constexpr (sizeof(T) == 4)
+    cast<double, float>(g.head, S, 0, [](Slot& s, CastArgs<double, float>& a) {
+      a.in = s.r;
+      a.out = (float*)s.lr[0];
+    }, SK);
+  else
+    vec<double>(g.head, S, 0, V_COPY, [](Slot& s, VecArgs<double>& a) {
+      a.x = (double*)s.lr[0];
+      a.r = s.r;
+    }, SK);
+
+  auto Tp = [](void* p) { return (T*)p; };
+
+  // one Chebyshev sweep at level l; from_zero: x0 = 0
+  auto sweep = [&](std::vector<Fn>& seq, int l, bool from_zero) {
+    const auto setv = [l, Tp](Slot& s, VecArgs<T>& a) {
+      a.r = Tp(s.lr[l]);
+      a.x = Tp(s.lx[l]);
+      a.res = Tp(s.lres[l]);
+      a.d = Tp(s.ld[l]);
+      a.t = Tp(s.lt[l]);
+      a.dinv = dinv_of<T>(s.level(l));
+    };
+    if (from_zero) {
+      vec<T>(seq, S, l, V_CHEB_INIT0, [l, setv](Slot& s, VecArgs<T>& a) {
+        setv(s, a);
+        a.c0 = 1.0 / s.pmg->lv[l].theta;
+      }, SK);
+    } else {
+      apply_A<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.lx[l]); }, [l, Tp](Slot& s) { return Tp(s.lt[l]); },
+                 false, SK);
+      vec<T>(seq, S, l, V_CHEB_INITX, [l, setv](Slot& s, VecArgs<T>& a) {
+        setv(s, a);
+        a.c0 = 1.0 / s.pmg->lv[l].theta;
+      }, SK);
+    }
+    for (int j = 1; j < K; ++j) {
+      apply_A<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.ld[l]); }, [l, Tp](Slot& s) { return Tp(s.lt[l]); },
+                 false, SK);
+      const VecOp op = (from_zero && j == 1) ? V_CHEB_STEP0 : V_CHEB_STEP;
+      vec<T>(seq, S, l, op, [l, j, setv](Slot& s, VecArgs<T>& a) {
+        setv(s, a);
+        a.c1 = s.pmg->lv[l].c1[j - 1];
+        a.c2 = s.pmg->lv[l].c2[j - 1];
+      }, SK);
+    }
+  };
+
+  // down-sweep
+  for (int l = 0; l + 1 < L; ++l) {
+    auto& seq = g.head;
+    if (o.pre > 0) {
+      sweep(seq, l, true);
+      for (int q = 1; q < o.pre; ++q) sweep(seq, l, false);
+      apply_A<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.lx[l]); }, [l, Tp](Slot& s) { return Tp(s.lt[l]); },
+                 false, SK);
+    } else {
+      vec<T>(seq, S, l, V_ZERO, [l, Tp](Slot& s, VecArgs<T>& a) { a.x = Tp(s.lx[l]); }, SK);
+    }
+    const bool pre = o.pre > 0;
+    if (l + 2 == L) {
+      xfer<T, double>(seq, S, l, 1, [l, Tp, pre](Slot& s, XferArgs<T, double>& a) {
+        a.rf = Tp(s.lr[l]);
+        a.tf = pre ? Tp(s.lt[l]) : nullptr;
+        a.owner_f = s.level(l).owner.as<uint8_t>();
+        a.out_c = s.cr;
+      }, SK);
+      gs<double>(seq, S, l + 1, [](Slot& s) { return s.cr; }, SK);
+    } else {
+      xfer<T, T>(seq, S, l, 1, [l, Tp, pre](Slot& s, XferArgs<T, T>& a) {
+        a.rf = Tp(s.lr[l]);
+        a.tf = pre ? Tp(s.lt[l]) : nullptr;
+        a.owner_f = s.level(l).owner.as<uint8_t>();
+        a.out_c = Tp(s.lr[l + 1]);
+      }, SK);
+      gs<T>(seq, S, l + 1, [l, Tp](Slot& s) { return Tp(s.lr[l + 1]); }, SK);
+    }
+  }
+
+  // coarse Jacobi-PCG, FP64
+  {
+    const int c = L - 1;
+    g.coarse_limit = o.coarse_fixed_iters > 0 ? o.coarse_fixed_iters : o.coarse_maxit;
+    g.coarse_fixed = o.coarse_fixed_iters;
+    g.coarse_check = o.coarse_check_every;
+    vec<double>(g.cinit, S, c, V_ZERO, [](Slot& s, VecArgs<double>& a) { a.x = s.cx; }, SK);
+    vec<double>(g.cinit, S, c, V_DOT1, [](Slot& s, VecArgs<double>& a) { a.r = s.cr; }, SK);
+    fin(g.cinit, S, FIN_INIT, 1, [c](Slot& s) { return vec_blocks(s.level(c).nloc); }, SK);
+    vec<double>(g.cinit, S, c, V_RZ_JACOBI, [c](Slot& s, VecArgs<double>& a) {
+      a.r = s.cr;
+      a.p = s.cp;
+      a.dinv = s.level(c).dinv64.as<double>();
+    }, SK);
+    fin(g.cinit, S, FIN_RZ, 1, [c](Slot& s) { return vec_blocks(s.level(c).nloc); }, SK);
+
+    apply_A<double>(g.citer, S, c, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2);
+    fin(g.citer, S, FIN_ALPHA, 1, [c](Slot& s) { return (int64_t)ax_blocks(s.level(c).N, s.level(c).E); }, 2);
+    vec<double>(g.citer, S, c, V_PCG_UPDATE, [c](Slot& s, VecArgs<double>& a) {
+      a.x = s.cx;
+      a.p = s.cp;
+      a.r = s.cr;
+      a.w = s.cw;
+      a.dinv = s.level(c).dinv64.as<double>();
+      a.scal = s.scal[1];
+    }, 2);
+    fin(g.citer, S, FIN_CHECK_JACOBI, 1, [c](Slot& s) { return vec_blocks(s.level(c).nloc); }, 2,
+        o.coarse_rtol, o.coarse_fixed_iters > 0 ? (1 << 30) : o.coarse_maxit, o.coarse_fixed_iters, true);
+    vec<double>(g.citer, S, c, V_P_JACOBI, [c](Slot& s, VecArgs<double>& a) {
+      a.p = s.cp;
+      a.r = s.cr;
+      a.dinv = s.level(c).dinv64.as<double>();
+      a.scal = s.scal[1];
+    }, 2);
+  }
+
+  // up-sweep
+  for (int l = L - 2; l >= 0; --l) {
+    auto& seq = g.tail;
+    if (l + 2 == L) {
+      xfer<T, double>(seq, S, l, 0, [l, Tp](Slot& s, XferArgs<T, double>& a) {
+        a.zc = s.cx;
+        a.xf = Tp(s.lx[l]);
+      }, SK);
+    } else {
+      xfer<T, T>(seq, S, l, 0, [l, Tp](Slot& s, XferArgs<T, T>& a) {
+        a.zc = Tp(s.lx[l + 1]);
+        a.xf = Tp(s.lx[l]);
+      }, SK);
+    }
+    for (int q = 0; q < o.post; ++q) sweep(seq, l, false);
+  }
+
+  if constexpr (sizeof(T) == 4)
+    cast<float, double>(g.tail, S, 0, [](Slot& s, CastArgs<float, double>& a) {
+      a.in = (const float*)s.lx[0];
+      a.out = s.z;
+    }, SK);
+  else
+    vec<double>(g.tail, S, 0, V_COPY, [](Slot& s, VecArgs<double>& a) {
+      a.x = s.z;
+      a.r = (double*)s.lx[0];
+    }, SK);
+}
+
+// outer flexible CG body (after the V-cycle has produced z from r)
+void Plan::build_flex(Group& g) {
+  auto& S = g.S;
+  if (S[0]->f32()) build_vcycle<float>(g); else build_vcycle<double>(g);
+  if (g.vcycle_only) return;
+  auto& t = g.tail;
+  vec<double>(t, S, 0, V_DOT2, [](Slot& s, VecArgs<double>& a) {
+    a.z = s.z;
+    a.w = s.w;
+    a.r = s.r;
+  }, 1);
+  fin(t, S, FIN_BETA_FLEX, 0, [](Slot& s) { return vec_blocks(s.level(0).nloc); }, 1);
+  vec<double>(t, S, 0, V_P_FLEX, [](Slot& s, VecArgs<double>& a) {
+    a.p = s.p;
+    a.z = s.z;
+    a.scal = s.scal[0];
+  }, 1);
+  apply_A<double>(t, S, 0, [](Slot& s) { return (const double*)s.p; }, [](Slot& s) { return s.w; }, true, 1);
+  fin(t, S, FIN_ALPHA, 0, [](Slot& s) { return (int64_t)ax_blocks(s.level(0).N, s.level(0).E); }, 1);
+  vec<double>(t, S, 0, V_PCG_UPDATE, [](Slot& s, VecArgs<double>& a) {
+    a.x = s.x;
+    a.p = s.p;
+    a.r = s.r;
+    a.w = s.w;
+    a.scal = s.scal[0];
+  }, 1);
+  fin(t, S, FIN_CHECK, 0, [](Slot& s) { return vec_blocks(s.level(0).nloc); }, 1);
+}
+
+void Plan::build_jacobi(Group& g) {
+  auto& S = g.S;
+  auto& h = g.head;
+  apply_A<double>(h, S, 0, [](Slot& s) { return (const double*)s.p; }, [](Slot& s) { return s.w; }, true, 1);
+  fin(h, S, FIN_ALPHA, 0, [](Slot& s) { return (int64_t)ax_blocks(s.level(0).N, s.level(0).E); }, 1);
+  vec<double>(h, S, 0, V_PCG_UPDATE, [](Slot& s, VecArgs<double>& a) {
+    a.x = s.x;
+    a.p = s.p;
+    a.r = s.r;
+    a.w = s.w;
+    a.dinv = s.level(0).dinv64.as<double>();
+    a.scal = s.scal[0];
+  }, 1);
+  fin(h, S, FIN_CHECK_JACOBI, 0, [](Slot& s) { return vec_blocks(s.level(0).nloc); }, 1);
+  vec<double>(h, S, 0, V_P_JACOBI, [](Slot& s, VecArgs<double>& a) {
+    a.p = s.p;
+    a.r = s.r;
+    a.dinv = s.level(0).dinv64.as<double>();
+    a.scal = s.scal[0];
+  }, 1);
+}
+
+// x = 0, r = b, ||b||; Jacobi: p = D^-1 r and (r, p); flexible CG: p = w = 0
+void Plan::build_init(Group& g) {
+  auto& S = g.S;
+  auto& q = g.init;
+  vec<double>(q, S, 0, V_ZERO, [](Slot& s, VecArgs<double>& a) { a.x = s.x; }, 0);
+  vec<double>(q, S, 0, V_COPY, [](Slot& s, VecArgs<double>& a) {
+    a.x = s.r;
+    a.r = const_cast<double*>(s.b);
+  }, 0);
+  vec<double>(q, S, 0, V_DOT1, [](Slot& s, VecArgs<double>& a) { a.r = s.r; }, 0);
+  fin(q, S, FIN_INIT, 0, [](Slot& s) { return vec_blocks(s.level(0).nloc); }, 0);
+  if (g.pmg) {
+    vec<double>(q, S, 0, V_ZERO, [](Slot& s, VecArgs<double>& a) { a.x = s.p; }, 0);
+    vec<double>(q, S, 0, V_ZERO, [](Slot& s, VecArgs<double>& a) { a.x = s.w; }, 0);
+  } else {
+    vec<double>(q, S, 0, V_RZ_JACOBI, [](Slot& s, VecArgs<double>& a) {
+      a.r = s.r;
+      a.p = s.p;
+      a.dinv = s.level(0).dinv64.as<double>();
+    }, 1);
+    fin(q, S, FIN_RZ, 0, [](Slot& s) { return vec_blocks(s.level(0).nloc); }, 1);
+  }
+}
+
+// group slots by solver structure
+static std::string signature(const Slot& s) {
+  if (!s.pmg) return "jacobi";
+  const sem_pmg_opts& o = s.pmg->o;
+  char buf[128];
+  snprintf(buf, sizeof(buf), "pmg L%d t%d k%d pre%d post%d cf%d cm%d cc%d", s.pmg->n_levels, (int)o.smoother_dtype,
+           o.cheb_degree, o.pre, o.post, o.coarse_fixed_iters, o.coarse_maxit, o.coarse_check_every);
+  return buf;
+}
+
+static std::unique_ptr<Plan> make_plan(const std::vector<Slot*>& slots, bool init, bool vcycle_only,
+                                       hipStream_t s) {
+  auto P = std::make_unique<Plan>();
+  std::map<std::string, std::vector<Slot*>> by;
+  for (Slot* sl : slots) by[signature(*sl)].push_back(sl);
+  P->groups.reserve(by.size());
+  for (auto& kv : by) {
+    P->groups.emplace_back();
+    Group& g = P->groups.back();
+    g.S = kv.second;
+    g.pmg = g.S[0]->pmg != nullptr;
+    g.L = g.S[0]->nlev();
+    g.vcycle_only = vcycle_only;
+    if (init) P->build_init(g);
+    else if (g.pmg) P->build_flex(g);
+    else P->build_jacobi(g);
+  }
+  P->upload(s);
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// batch
+// ---------------------------------------------------------------------------
+}  // namespace sem
+
+struct sem_batch_s {
+  hipStream_t stream = nullptr;
+  int max_slots = 0;
+  std::vector<sem::Slot> slots;
+  sem::DevBuf ctrl;             // per slot: 2 x S_COUNT doubles, then 2 x F_COUNT ints
+  void* host_ctrl = nullptr;    // pinned mirror
+  size_t ctrl_bytes = 0;
+  std::unique_ptr<sem::Plan> plan;
+  bool dirty = true;
+
+  size_t scal_bytes() const { return sizeof(double) * 2 * sem::S_COUNT * max_slots; }
+  ~sem_batch_s() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto& s : slots) sem::pool_put(s.ws, s.ws_bytes);
+    if (host_ctrl) (void)hipHostFree(host_ctrl);
+  }
+};
+
+namespace sem {
+
+static void batch_init(sem_batch_s* B, int max_slots, hipStream_t s) {
+  B->stream = s;
+  B->max_slots = max_slots;
+  B->slots.resize(max_slots);
+  B->ctrl_bytes = B->scal_bytes() + sizeof(int) * 2 * F_COUNT * max_slots;
+  B->ctrl.alloc(B->ctrl_bytes);
+  SEM_HIP(hipMemsetAsync(B->ctrl.p, 0, B->ctrl_bytes, s));
+  SEM_HIP(hipHostMalloc(&B->host_ctrl, B->ctrl_bytes, hipHostMallocDefault));
+  for (int k = 0; k < max_slots; ++k) {
+    Slot& sl = B->slots[k];
+    sl.idx = k;
+    double* sc = B->ctrl.as<double>() + (size_t)2 * S_COUNT * k;
+    int* fl = reinterpret_cast<int*>(B->ctrl.as<uint8_t>() + B->scal_bytes()) + (size_t)2 * F_COUNT * k;
+    sl.scal[0] = sc;
+    sl.scal[1] = sc + S_COUNT;
+    sl.flags[0] = fl;
+    sl.flags[1] = fl + F_COUNT;
+  }
+}
+
+static void fetch_ctrl(sem_batch_s* B) {
+  SEM_HIP(hipMemcpyAsync(B->host_ctrl, B->ctrl.p, B->ctrl_bytes, hipMemcpyDeviceToHost, B->stream));
+  SEM_HIP(hipStreamSynchronize(B->stream));
+}
+static const double* host_scal(sem_batch_s* B, int k, int stage) {
+  return static_cast<const double*>(B->host_ctrl) + (size_t)2 * S_COUNT * k + (size_t)stage * S_COUNT;
+}
+static const int* host_flags(sem_batch_s* B, int k, int stage) {
+  return reinterpret_cast<const int*>(static_cast<const uint8_t*>(B->host_ctrl) + B->scal_bytes()) +
+         (size_t)2 * F_COUNT * k + (size_t)stage * F_COUNT;
+}
+
+static void run(const std::vector<Fn>& seq, hipStream_t s) {
+  for (const Fn& f : seq) f(s);
+}
+
+// one pass of every group's body; the coarse loop polls its done flags
+static void run_body(sem_batch_s* B, Plan& P) {
+  for (Group& g : P.groups) {
+    run(g.head, B->stream);
+    if (!g.cinit.empty()) {
+      run(g.cinit, B->stream);
+      int ran = 0;
+      while (ran < g.coarse_limit) {
+        const int chunk = g.coarse_fixed > 0 ? g.coarse_limit : std::min(g.coarse_check, g.coarse_limit - ran);
+        for (int k = 0; k < chunk; ++k) run(g.citer, B->stream);
+        ran += chunk;
+        if (ran >= g.coarse_limit) break;
+        fetch_ctrl(B);
+        bool all = true;
+        for (Slot* s : g.S)
+          if (!host_flags(B, s->idx, 0)[F_DONE] && !host_flags(B, s->idx, 1)[F_DONE]) all = false;
+        if (all) break;
+      }
+    }
+    run(g.tail, B->stream);
+  }
+}
+
+static double true_relres(Slot& s, hipStream_t st) {
+  const MeshData& m = s.level(0);
+  apply_A(m, SEM_F64, s.x, s.w, st);
+  Table<VecArgs<double>> t;
+  t.one.n = m.nloc;
+  t.one.r = const_cast<double*>(s.b);
+  t.one.t = s.w;
+  t.one.owner = m.owner.as<uint8_t>();
+  t.one.partial = s.partial;
+  t.one.stride = s.stride;
+  const int64_t nb = vec_blocks(m.nloc);
+  launch_vec<double>(V_TRUE_RES, t, nb, st);
+  std::vector<double> h(nb);
+  SEM_HIP(hipMemcpyAsync(h.data(), s.partial, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+  SEM_HIP(hipStreamSynchronize(st));
+  double sum = 0.0;
+  for (double v : h) sum += v;
+  return sum;
+}
+
+static void batch_add(sem_batch_s* B, sem_mesh m, sem_pmg p, const double* b, double* x, const sem_solve_opts* oin,
+                      int* slot_out) {
+  if (!m || !b || !x) fail(SEM_EINVAL, "batch add: NULL argument");
+  if (p && p->base != m) fail(SEM_EINVAL, "batch add: the pMG hierarchy was built on another mesh");
+  int k = -1;
+  for (int q = 0; q < B->max_slots; ++q)
+    if (B->slots[q].state == 0) { k = q; break; }
+  if (k < 0) fail(SEM_EBUSY, "batch add: all %d slots are in use", B->max_slots);
+  Slot& s = B->slots[k];
+  s.mesh = m;
+  s.pmg = p;
+  s.b = b;
+  s.x = x;
+  sem_solve_opts_default(&s.o);
+  if (oin) s.o = *oin;
+  if (!(s.o.rtol >= 0)) fail(SEM_EINVAL, "batch add: rtol must be >= 0");
+  if (s.o.maxit < 1) s.o.maxit = 1;
+  if (s.o.check_every < 1) s.o.check_every = 1;
+  const size_t bytes = layout(s, nullptr);
+  s.ws = pool_get(bytes);
+  s.ws_bytes = bytes;
+  layout(s, static_cast<uint8_t*>(s.ws));
+  s.state = 1;
+  s.info = sem_solve_info{};
+  s.info.status = 1;
+  s.t0 = Clock::now();
+  SEM_HIP(hipMemsetAsync(s.scal[0], 0, sizeof(double) * 2 * S_COUNT, B->stream));
+  SEM_HIP(hipMemsetAsync(s.flags[0], 0, sizeof(int) * 2 * F_COUNT, B->stream));
+  B->dirty = true;
+  if (slot_out) *slot_out = k;
+}
+
+static void batch_release(sem_batch_s* B, int k) {
+  if (k < 0 || k >= B->max_slots) fail(SEM_EINVAL, "batch release: slot %d out of range", k);
+  Slot& s = B->slots[k];
+  if (s.state == 0) return;
+  SEM_HIP(hipStreamSynchronize(B->stream));
+  pool_put(s.ws, s.ws_bytes);
+  s.ws = nullptr;
+  s.ws_bytes = 0;
+  if (s.state == 1 || s.state == 2) B->dirty = true;
+  s.state = 0;
+  s.mesh = nullptr;
+  s.pmg = nullptr;
+}
+
+static void finish_slot(sem_batch_s* B, Slot& s) {
+  const double* sc = host_scal(B, s.idx, 0);
+  const int* fl = host_flags(B, s.idx, 0);
+  s.info.iters = fl[F_ITERS];
+  s.info.status = fl[F_STATUS];
+  s.info.relres = sc[S_RELRES];
+  s.info.coarse_iters = fl[F_TOTAL];
+  const double bb = sc[S_BB];
+  if (bb > 0 && std::isfinite(bb) && s.info.status != SEM_ENAN) {
+    s.info.relres_true = std::sqrt(true_relres(s, B->stream) / bb);
+  } else {
+    s.info.relres_true = (bb == 0) ? 0.0 : NAN;
+  }
+  s.info.seconds = std::chrono::duration<double>(Clock::now() - s.t0).count();
+  s.state = 3;
+}
+
+static int batch_step(sem_batch_s* B, int iters) {
+  // initialise newly admitted solves
+  std::vector<Slot*> fresh;
+  for (Slot& s : B->slots)
+    if (s.state == 1) fresh.push_back(&s);
+  if (!fresh.empty()) {
+    auto P = make_plan(fresh, true, false, B->stream);
+    for (Group& g : P->groups) run(g.init, B->stream);
+    SEM_HIP(hipStreamSynchronize(B->stream));
+    for (Slot* s : fresh) s->state = 2;
+    B->dirty = true;
+  }
+  std::vector<Slot*> act;
+  for (Slot& s : B->slots)
+    if (s.state == 2) act.push_back(&s);
+  if (act.empty()) return 0;
+  // problems that are already done after init (zero or NaN rhs) retire now
+  fetch_ctrl(B);
+  {
+    std::vector<Slot*> still;
+    for (Slot* s : act) {
+      if (host_flags(B, s->idx, 0)[F_DONE]) { finish_slot(B, *s); B->dirty = true; }
+      else still.push_back(s);
+    }
+    act.swap(still);
+  }
+  if (act.empty()) return 0;
+  if (B->dirty || !B->plan) {
+    SEM_HIP(hipStreamSynchronize(B->stream));
+    B->plan = make_plan(act, false, false, B->stream);
+    B->dirty = false;
+  }
+  for (int it = 0; it < iters; ++it) run_body(B, *B->plan);
+  fetch_ctrl(B);
+  int n_active = 0;
+  for (Slot* s : act) {
+    if (host_flags(B, s->idx, 0)[F_DONE]) {
+      finish_slot(B, *s);
+      B->dirty = true;
+    } else {
+      ++n_active;
+    }
+  }
+  return n_active;
+}
+
+}  // namespace sem
+
+using namespace sem;
+
+extern "C" void sem_solve_opts_default(sem_solve_opts* o) {
+  if (!o) return;
+  *o = sem_solve_opts{};
+  o->rtol = 1e-8;
+  o->maxit = 10000;
+  o->check_every = 1;
+  o->fixed_iters = 0;
+}
+
+extern "C" size_t sem_solve_workspace_bytes(sem_mesh m, sem_pmg p) {
+  if (!m) return 0;
+  try {
+    Slot s;
+    s.mesh = m;
+    s.pmg = p;
+    return layout(s, nullptr);
+  } catch (...) {
+    return 0;
+  }
+}
+
+extern "C" int sem_batch_create(int max_slots, void* stream, sem_batch* out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out || max_slots < 1) fail(SEM_EINVAL, "sem_batch_create: bad argument");
+    auto B = std::make_unique<sem_batch_s>();
+    batch_init(B.get(), max_slots, (hipStream_t)stream);
+    *out = B.release();
+  });
+}
+
+extern "C" int sem_batch_destroy(sem_batch b) {
+  return guarded([&] { delete b; });
+}
+
+extern "C" int sem_batch_add(sem_batch b, sem_mesh m, sem_pmg p, const double* rhs, double* x,
+                             const sem_solve_opts* o, int* slot) {
+  return guarded([&] {
+    if (!b) fail(SEM_EINVAL, "sem_batch_add: NULL batch");
+    batch_add(b, m, p, rhs, x, o, slot);
+  });
+}
+
+extern "C" int sem_batch_step(sem_batch b, int iters, int* n_active) {
+  return guarded([&] {
+    if (!b) fail(SEM_EINVAL, "sem_batch_step: NULL batch");
+    const int n = batch_step(b, iters < 1 ? 1 : iters);
+    if (n_active) *n_active = n;
+  });
+}
+
+extern "C" int sem_batch_poll(sem_batch b, int slot, sem_solve_info* info) {
+  return guarded([&] {
+    if (!b || !info) fail(SEM_EINVAL, "sem_batch_poll: NULL argument");
+    if (slot < 0 || slot >= b->max_slots) fail(SEM_EINVAL, "sem_batch_poll: slot %d out of range", slot);
+    const Slot& s = b->slots[slot];
+    *info = s.info;
+    if (s.state == 1 || s.state == 2) info->status = 1;
+    if (s.state == 0) fail(SEM_EINVAL, "sem_batch_poll: slot %d is free", slot);
+  });
+}
+
+extern "C" int sem_batch_release(sem_batch b, int slot) {
+  return guarded([&] {
+    if (!b) fail(SEM_EINVAL, "sem_batch_release: NULL batch");
+    batch_release(b, slot);
+  });
+}
+
+static int solve_many(int n, const sem_mesh* m, const sem_pmg* p, const double* const* b, double* const* x,
+                      const sem_solve_opts* o, sem_solve_info* info, void* stream) {
+  sem_batch_s B;
+  batch_init(&B, n, (hipStream_t)stream);
+  const auto t0 = Clock::now();
+  for (int k = 0; k < n; ++k) batch_add(&B, m[k], p ? p[k] : nullptr, b[k], x[k], o, nullptr);
+  const int every = (o && o->check_every > 0) ? o->check_every : 1;
+  int64_t cap = 0;
+  for (int k = 0; k < n; ++k) cap = std::max<int64_t>(cap, std::max(B.slots[k].o.maxit, B.slots[k].o.fixed_iters));
+  int64_t ran = 0;
+  // the device marks every problem done by maxit; the host bound is a backstop
+  while (batch_step(&B, every) > 0) {
+    ran += every;
+    if (ran > cap + 2 * every + 8) fail(SEM_EHIP, "solve: device convergence flags did not settle");
+  }
+  int worst = SEM_OK;
+  const double secs = std::chrono::duration<double>(Clock::now() - t0).count();
+  for (int k = 0; k < n; ++k) {
+    Slot& s = B.slots[k];
+    if (info) {
+      info[k] = s.info;
+      info[k].seconds = secs;
+    }
+    if (s.info.status < 0 && worst == SEM_OK) worst = s.info.status;
+  }
+  if (worst == SEM_ENOCONV) set_error("solve: iteration limit reached");
+  if (worst == SEM_ENAN) set_error("solve: NaN or Inf in the right-hand side or an iterate");
+  return worst;
+}
+
+extern "C" int sem_pcg_solve(sem_mesh m, sem_pmg p, const double* b, double* x, const sem_solve_opts* o,
+                             sem_solve_info* info, void* stream) {
+  int rc = SEM_OK;
+  int g = guarded([&] {
+    if (!m || !b || !x) fail(SEM_EINVAL, "sem_pcg_solve: NULL argument");
+    rc = solve_many(1, &m, p ? &p : nullptr, &b, &x, o, info, stream);
+  });
+  return g != SEM_OK ? g : rc;
+}
+
+extern "C" int sem_pcg_solve_batched(int n, const sem_mesh* m, const sem_pmg* p, const double* const* b,
+                                     double* const* x, const sem_solve_opts* o, sem_solve_info* info, void* stream) {
+  int rc = SEM_OK;
+  int g = guarded([&] {
+    if (n < 1 || !m || !b || !x) fail(SEM_EINVAL, "sem_pcg_solve_batched: bad argument");
+    rc = solve_many(n, m, p, b, x, o, info, stream);
+  });
+  return g != SEM_OK ? g : rc;
+}
+
+extern "C" int sem_pmg_apply(sem_pmg p, const double* r, double* z, void* stream) {
+  return guarded([&] {
+    if (!p || !r || !z) fail(SEM_EINVAL, "sem_pmg_apply: NULL argument");
+    sem_batch_s B;
+    batch_init(&B, 1, (hipStream_t)stream);
+    Slot& s = B.slots[0];
+    s.mesh = p->base;
+    s.pmg = p;
+    const size_t bytes = layout(s, nullptr);
+    s.ws = pool_get(bytes);
+    s.ws_bytes = bytes;
+    layout(s, static_cast<uint8_t*>(s.ws));
+    s.state = 2;
+    // the V-cycle reads slot.r and writes slot.z: copy r in, z out
+    SEM_HIP(hipMemcpyAsync(s.r, r, sizeof(double) * p->base->d.nloc, hipMemcpyDeviceToDevice, B.stream));
+    std::vector<Slot*> one{&s};
+    auto P = make_plan(one, false, true, B.stream);
+    run_body(&B, *P);
+    SEM_HIP(hipMemcpyAsync(z, s.z, sizeof(double) * p->base->d.nloc, hipMemcpyDeviceToDevice, B.stream));
+    SEM_HIP(hipStreamSynchronize(B.stream));
+  });
+}
+
+extern "C" int sem_pmg_transfer(sem_pmg p, int level, int direction, const void* in, void* out, void* stream) {
+  return guarded([&] {
+    if (!p || !in || !out) fail(SEM_EINVAL, "sem_pmg_transfer: NULL argument");
+    if (level < 0 || level + 1 >= p->n_levels) fail(SEM_EINVAL, "sem_pmg_transfer: level %d out of range", level);
+    if (direction != 0 && direction != 1) fail(SEM_EINVAL, "sem_pmg_transfer: direction must be 0 or 1");
+    hipStream_t s = (hipStream_t)stream;
+    const MeshData& f = p->lv[level].mesh->d;
+    const MeshData& c = p->lv[level + 1].mesh->d;
+    const bool f32 = p->o.smoother_dtype == SEM_F32;
+    const bool coarse_is_last = (level + 2 == p->n_levels);
+    const int64_t nb = xfer_blocks(f.N, c.N, f.E);
+    const double* M = direction == 0 ? p->lv[level].J.as<double>() : p->lv[level].JT.as<double>();
+    auto gs_c = [&](auto* v) {
+      using T = std::remove_pointer_t<decltype(v)>;
+      Table<GsArgs<T>> t;
+      t.one.v = v;
+      t.one.off = c.gs_off.as<int>();
+      t.one.idx = c.gs_idx.as<int>();
+      t.one.sdir = c.gs_dir.as<uint8_t>();
+      t.one.dir_idx = c.dir_idx.as<int>();
+      t.one.n_shared = c.n_shared;
+      t.one.n_dir = c.n_dir_single;
+      t.one.mask = 1;
+      launch_gs<T>(t, gs_blocks(c.n_shared, c.n_dir_single), s);
+    };
+    auto go = [&](auto tf, auto tc) {
+      using Tf = decltype(tf);
+      using Tc = decltype(tc);
+      Table<XferArgs<Tf, Tc>> t;
+      t.one.E = f.E;
+      if (direction == 0) {
+        t.one.zc = (const Tc*)in;
+        t.one.xf = (Tf*)out;
+      } else {
+        t.one.rf = (const Tf*)in;
+        t.one.owner_f = f.owner.as<uint8_t>();
+        t.one.out_c = (Tc*)out;
+      }
+      launch_xfer<Tf, Tc>(direction, f.N, c.N, t, nb, M, s);
+      if (direction == 1) gs_c((Tc*)out);
+    };
+    if (f32 && coarse_is_last) go(float{}, double{});
+    else if (f32) go(float{}, float{});
+    else go(double{}, double{});
+  });
+}

@@ -1,0 +1,324 @@
+// Internal declarations shared by the libsem sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "sem.h"
+
+namespace sem {
+
+constexpr int kMaxN = 15;
+constexpr int kMaxNP = kMaxN + 1;
+constexpr int kMaxLevels = 8;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error {
+  int code;
+};
+void set_error(const char* fmt, ...);
+[[noreturn]] void fail(int code, const char* fmt, ...);
+
+#define SEM_HIP(call)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      ::sem::fail(e_ == hipErrorOutOfMemory ? SEM_ENOMEM : SEM_EHIP, "%s: %s (%s:%d)",   \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+// C-ABI wrapper: runs f, turns sem::Error into its status code.
+template <typename F>
+int guarded(F&& f) {
+  try {
+    f();
+    return SEM_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error("internal error: %s", e.what());
+    return SEM_EHIP;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reference element (host, FP64)
+// ---------------------------------------------------------------------------
+void gll_points(int N, double* x, double* w);
+void deriv_matrix(int N, double* D);  // row-major (N+1)x(N+1)
+void lagrange_matrix(int n_src, const double* src, int n_dst, const double* dst, double* M);
+
+// 1D matrix passed by value to kernels (copied to LDS there).
+template <typename T>
+struct Mat1D {
+  T a[kMaxNP * kMaxNP];
+};
+
+// ---------------------------------------------------------------------------
+// device memory helper
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n);
+  void release();
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// one mesh level, resident on the device
+// ---------------------------------------------------------------------------
+struct MeshData {
+  int N = 0, NP = 0, Np = 0;
+  int64_t E = 0, nloc = 0;
+  int64_t n_unique = 0, n_interior = 0, n_shared = 0, n_shared_entries = 0, n_dir_single = 0;
+  double min_detJ = 0, volume = 0;
+  std::vector<double> D;   // (N+1)^2 host copy
+  std::vector<double> w;   // GLL weights
+  DevBuf Dg64, Dg32, wg;   // device copies of Dhat (FP64, FP32) and the weights
+  DevBuf x, y, z;          // double [nloc]
+  DevBuf gid;              // int64 [nloc]
+  DevBuf dmask;            // uint8 [nloc]  1 = Dirichlet copy
+  DevBuf owner;            // uint8 [nloc]  1 = first copy of its ID (0 on Dirichlet)
+  DevBuf G64, G32;         // [E][6][Np]
+  DevBuf B64, B32;         // [E][Np]
+  DevBuf dinv64, dinv32;   // [nloc]
+  DevBuf gs_off;           // int32 [n_shared+1]
+  DevBuf gs_idx;           // int32 [n_shared_entries]
+  DevBuf gs_dir;           // uint8 [n_shared]  1 = Dirichlet node
+  DevBuf dir_idx;          // int32 [n_dir_single]  Dirichlet copies of unshared IDs
+  int64_t resident_bytes() const;
+};
+
+}  // namespace sem
+
+struct sem_mesh_s {
+  sem::MeshData d;
+  bool owned_by_pmg = false;
+};
+
+namespace sem {
+
+// ---------------------------------------------------------------------------
+// kernel argument tables: a launch covers one problem (inline args) or many
+// (device array of args + block prefix `starts[n+1]`)
+// ---------------------------------------------------------------------------
+template <typename A>
+struct Table {
+  A one;
+  const A* many = nullptr;
+  const int* starts = nullptr;
+  int n = 0;
+};
+
+// skip flags: a problem's launch does nothing when either flag is nonzero
+struct Skip {
+  const int* f0 = nullptr;
+  const int* f1 = nullptr;
+};
+
+template <typename T>
+struct AxArgs {
+  const T* G = nullptr;
+  const T* B = nullptr;   // Helmholtz mass factor, or null
+  const T* u = nullptr;
+  T* Au = nullptr;
+  int64_t e0 = 0, ne = 0;
+  double lambda = 0;
+  double* partial = nullptr;  // per block: sum u . Au over the block's points
+  Skip skip;
+};
+
+template <typename T>
+struct GsArgs {
+  T* v = nullptr;
+  const int* off = nullptr;
+  const int* idx = nullptr;
+  const uint8_t* sdir = nullptr;
+  const int* dir_idx = nullptr;
+  int64_t n_shared = 0, n_dir = 0;
+  int mask = 1;
+  Skip skip;
+};
+
+enum VecOp : int {
+  V_PCG_UPDATE = 0,   // x += a p; r -= a w; partial0 = own r.r; partial1 = own r.dinv.r (Jacobi)
+  V_P_JACOBI,         // p = dinv r + beta p
+  V_P_FLEX,           // p = z + beta p
+  V_DOT2,             // partial0 = own z.w ; partial1 = own r.z
+  V_DOT1,             // partial0 = own r.r  (r = x slot a)
+  V_RZ_JACOBI,        // partial0 = own r.dinv.r ; p = dinv r
+  V_CHEB_INIT0,       // d = dinv r / theta; x = d           (pre-smoothing start)
+  V_CHEB_INITX,       // res = r - t; d = dinv res / theta; x += d
+  V_CHEB_STEP,        // res -= t; d = c1 d + c2 dinv res; x += d
+  V_CHEB_STEP0,       // first step after INIT0: res = r - t; d = c1 d + c2 dinv res; x += d
+  V_ZERO,             // x = 0
+  V_COPY,             // x = r
+  V_SCALE_DINV,       // x = dinv * r
+  V_NORMALIZE,        // x = r * scal[S_TMP]
+  V_TRUE_RES,         // partial0 = own (r - t).(r - t)
+  V_DIV_DINV,         // x = r / dinv (0 where dinv = 0)
+  V_SCALE,            // x = c0 r
+  V_COUNT
+};
+
+// scalar slots of a solve stage (per problem, device doubles)
+enum Scal : int {
+  S_BB = 0, S_RZ, S_PW, S_ALPHA, S_BETA, S_RR, S_RELRES, S_ZW, S_TMP, S_RZ_NEW, S_COUNT
+};
+// integer flags of a solve stage
+enum Flag : int { F_DONE = 0, F_STATUS, F_ITERS, F_TOTAL, F_COUNT };
+
+template <typename T>
+struct VecArgs {
+  int64_t n = 0;
+  T* x = nullptr;
+  T* r = nullptr;
+  T* p = nullptr;
+  T* w = nullptr;
+  T* z = nullptr;
+  T* t = nullptr;
+  T* res = nullptr;
+  T* d = nullptr;
+  const T* dinv = nullptr;
+  const uint8_t* owner = nullptr;
+  const double* scal = nullptr;
+  double* partial = nullptr;  // [2][stride]
+  int64_t stride = 0;
+  double c0 = 0, c1 = 0, c2 = 0;
+  Skip skip;
+};
+
+template <typename Tin, typename Tout>
+struct CastArgs {
+  int64_t n = 0;
+  const Tin* in = nullptr;
+  Tout* out = nullptr;
+  Skip skip;
+};
+
+enum FinOp : int {
+  FIN_INIT = 0,       // bb = s0; rr = bb; detect zero / NaN rhs
+  FIN_RZ,             // rz = s0; beta = 0
+  FIN_ALPHA,          // pw = s0; alpha = rz / pw
+  FIN_CHECK,          // rr = s0; iters++; convergence test
+  FIN_CHECK_JACOBI,   // as FIN_CHECK plus beta = s1 / rz, rz = s1
+  FIN_BETA_FLEX,      // zw = s0, rz_new = s1; beta = -alpha zw / rz; rz = rz_new
+  FIN_NORM,           // tmp = 1 / sqrt(s0)
+  FIN_STORE           // tmp = s0
+};
+
+struct FinArgs {
+  const double* partial = nullptr;  // [2][stride]
+  int64_t stride = 0;
+  int64_t nblk = 0;
+  double* scal = nullptr;
+  int* flags = nullptr;
+  double rtol = 0;
+  int maxit = 0;
+  int fixed = 0;
+  int* total = nullptr;             // optional counter incremented with iters (coarse total)
+  Skip skip;
+};
+
+template <typename Tf, typename Tc>
+struct XferArgs {
+  int64_t E = 0;
+  // restrict: out_c = (J^T)^3 ((rf - tf) . owner_f)   (tf may be null)
+  const Tf* rf = nullptr;
+  const Tf* tf = nullptr;
+  const uint8_t* owner_f = nullptr;
+  Tc* out_c = nullptr;
+  // prolong: xf += J^3 zc
+  const Tc* zc = nullptr;
+  Tf* xf = nullptr;
+  Skip skip;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (defined in sem_kernels.hip)
+// ---------------------------------------------------------------------------
+int ax_blocks(int N, int64_t ne);
+int64_t vec_blocks(int64_t n);
+int64_t gs_blocks(int64_t n_shared, int64_t n_dir);
+int xfer_blocks(int Nf, int Nc, int64_t E);
+constexpr int kFinThreads = 256;
+
+template <typename T>
+void launch_ax(int N, const Table<AxArgs<T>>& t, int64_t total_blocks, const T* D, hipStream_t s);
+template <typename T>
+void launch_gs(const Table<GsArgs<T>>& t, int64_t total_blocks, hipStream_t s);
+template <typename T>
+void launch_vec(VecOp op, const Table<VecArgs<T>>& t, int64_t total_blocks, hipStream_t s);
+template <typename Tin, typename Tout>
+void launch_cast(const Table<CastArgs<Tin, Tout>>& t, int64_t total_blocks, hipStream_t s);
+void launch_fin(FinOp op, const Table<FinArgs>& t, int nprob, hipStream_t s);
+template <typename Tf, typename Tc>
+void launch_xfer(int dir, int Nf, int Nc, const Table<XferArgs<Tf, Tc>>& t, int64_t total_blocks,
+                 const double* J, hipStream_t s);
+
+// setup kernels
+void launch_geometry(const MeshData& m, double* detmin_partial, double* vol_partial, int64_t* bad_index,
+                     hipStream_t s);
+void launch_diag_local(const MeshData& m, double* dl, hipStream_t s);
+void launch_dinv_finish(const MeshData& m, const double* d_assembled, hipStream_t s);
+void launch_tensor_coords(int Nf, int Nc, int64_t E, const double* in, double* out, const double* Jcf,
+                          hipStream_t s);
+void launch_start_vector(int64_t n, const int64_t* gid, const uint8_t* dmask, double* v, hipStream_t s);
+void launch_mass(int N, int64_t nloc, int is_f32, const void* B, const void* u, void* Bu, hipStream_t s);
+
+// gather-scatter map construction (sem_gsmap.hip)
+void build_gs_map(MeshData& m, hipStream_t s);
+
+// mesh construction from device coordinates and host IDs/flags (sem_mesh.cpp)
+void build_mesh(MeshData& m, int N, int64_t E, const int64_t* gid_host, const uint8_t* dir_host,
+                hipStream_t s);
+
+// deterministic dot product on one mesh (FP64 result), synchronous
+double mesh_dot(const MeshData& m, sem_dtype t, const void* a, const void* b, hipStream_t s);
+
+// single-problem helpers used by setup code
+void apply_A(const MeshData& m, sem_dtype t, const void* u, void* Au, hipStream_t s);
+
+}  // namespace sem
+
+// ---------------------------------------------------------------------------
+// p-multigrid hierarchy
+// ---------------------------------------------------------------------------
+namespace sem {
+struct PmgLevel {
+  sem_mesh_s* mesh = nullptr;    // level mesh (level 0: the user's mesh)
+  double rho = 0, theta = 0, delta = 0;
+  std::vector<double> c1, c2;    // Chebyshev step coefficients, steps 1..k-1
+  DevBuf J;                      // prolongation from level l+1: (N_l+1) x (N_{l+1}+1)
+  DevBuf JT;                     // restriction to level l+1:   (N_{l+1}+1) x (N_l+1)
+};
+void chebyshev_coefficients(PmgLevel& lv, double lo, double hi, int degree);
+}  // namespace sem
+
+struct sem_pmg_s {
+  sem_mesh base = nullptr;
+  sem_pmg_opts o{};
+  int n_levels = 0;
+  int orders[sem::kMaxLevels] = {0};
+  std::vector<sem::PmgLevel> lv;
+  std::vector<sem_mesh_s*> owned;   // coarse level meshes (deleted with the hierarchy)
+  ~sem_pmg_s() {
+    for (sem_mesh_s* m : owned) delete m;
+  }
+};

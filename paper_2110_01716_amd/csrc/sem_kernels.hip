@@ -1,0 +1,833 @@
+// HIP kernels of the SEM Poisson solve for gfx950 (MI355X).
+//
+//  * k_ax      matrix-free local Laplacian A_L u = sum_m D_m^T sum_n G_mn D_n u
+//              (the paper's "Ax", Performance Measurements, per-kernel table).
+//              Thread (i,j) of an element owns the GLL column (i,j,0..N): the t
+//              derivative and its transpose run in registers, the r and s
+//              derivatives read the element staged in LDS. G is streamed once,
+//              coalesced (64 consecutive points per instruction at N=7).
+//  * k_gs      direct-stiffness summation QQ^T with the Dirichlet mask fused in
+//              (exchange-and-sum of shared values, Implementation, Autotuned
+//              Communication). One thread per shared node, copies summed in
+//              ascending local-index order.
+//  * k_vec     fused PCG / flexible-CG / Chebyshev vector updates with
+//              deterministic per-block partial dot products.
+//  * k_fin     per-problem reduction of the partials in a fixed order plus the
+//              scalar recurrences (alpha, beta, convergence tests).
+//  * k_xfer    pMG prolongation (J x J x J) and restriction (transpose), sum
+//              factorised in LDS (Implementation, pMG paragraph).
+//  * setup     geometric factors, Jacobi diagonal, start vectors, coordinates.
+//
+// Every kernel accepts a Table: either inline arguments for one problem or a
+// device array of per-problem arguments with block prefix offsets, so one
+// launch can serve many independent solves (blocks never straddle problems,
+// so each problem's arithmetic is independent of the others).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "sem_internal.h"
+
+namespace sem {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+template <typename A>
+__device__ __forceinline__ A fetch_args(const Table<A>& t, int b, int& lb) {
+  if (t.many == nullptr) {
+    lb = b;
+    return t.one;
+  }
+  int lo = 0, hi = t.n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (t.starts[mid] <= b) lo = mid; else hi = mid;
+  }
+  lb = b - t.starts[lo];
+  return t.many[lo];
+}
+
+__device__ __forceinline__ bool skipped(const Skip& s) {
+  return (s.f0 && *(volatile const int*)s.f0) || (s.f1 && *(volatile const int*)s.f1);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block sum with a fixed order (wave butterfly, then waves in index order);
+// result valid in thread 0. scratch: >= nwaves doubles of LDS.
+template <int THREADS>
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  v = wave_sum(v);
+  constexpr int NW = (THREADS + 63) / 64;
+  if constexpr (NW == 1) {
+    return v;
+  } else {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+      for (int k = 0; k < NW; ++k) s += scratch[k];
+    return s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Ax
+// ---------------------------------------------------------------------------
+template <int N>
+struct AxCfg {
+  static constexpr int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
+  static constexpr int EPB = N == 1 ? 64 : N == 2 ? 28 : N == 3 ? 16 : N == 4 ? 10 : N == 5 ? 7
+                           : N == 6 ? 5 : N == 7 ? 1 : N == 8 ? 3 : N == 9 ? 2 : N == 10 ? 2 : 1;
+  static constexpr int THREADS = ((EPB * NP2 + 63) / 64) * 64;
+  static constexpr int NPAD = NP | 1;  // odd row stride: conflict-free column reads
+};
+
+template <int N, typename T>
+__global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, const T* __restrict__ Dg) {
+  using C = AxCfg<N>;
+  constexpr int NP = C::NP, NP2 = C::NP2, NP3 = C::NP3, EPB = C::EPB, NPAD = C::NPAD;
+  __shared__ T s_u[EPB][NP][NP][NPAD];
+  __shared__ T s_wr[EPB][NP][NP][NPAD];
+  __shared__ T s_ws[EPB][NP][NP][NPAD];
+  __shared__ double s_red[C::THREADS / 64];
+
+  int lb;
+  const AxArgs<T> a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+
+  const int tid = threadIdx.x;
+  const int el = tid / NP2;
+  const int ij = tid - el * NP2;
+  const int i = ij % NP, j = ij / NP;
+  const int64_t el_local = (int64_t)lb * EPB + el;
+  const bool active = (el < EPB) && (el_local < a.ne);
+  const int elc = el < EPB ? el : 0;
+  const int64_t e = a.e0 + el_local;
+
+  T Dr[NP], Ds[NP], DrT[NP], DsT[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    Dr[q] = Dg[i * NP + q];
+    Ds[q] = Dg[j * NP + q];
+    DrT[q] = Dg[q * NP + i];
+    DsT[q] = Dg[q * NP + j];
+  }
+
+  T uk[NP];
+  if (active) {
+    const T* up = a.u + e * NP3 + ij;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      uk[k] = up[k * NP2];
+      s_u[elc][k][j][i] = uk[k];
+    }
+  }
+  __syncthreads();
+
+  T wt[NP];
+  if (active) {
+    const T* g = a.G + e * 6 * NP3 + ij;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      T ur = 0, us = 0, ut = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        ur += Dr[q] * s_u[elc][k][j][q];
+        us += Ds[q] * s_u[elc][k][q][i];
+        ut += Dg[k * NP + q] * uk[q];
+      }
+      const T grr = g[k * NP2], grs = g[NP3 + k * NP2], grt = g[2 * NP3 + k * NP2];
+      const T gss = g[3 * NP3 + k * NP2], gst = g[4 * NP3 + k * NP2], gtt = g[5 * NP3 + k * NP2];
+      s_wr[elc][k][j][i] = grr * ur + grs * us + grt * ut;
+      s_ws[elc][k][j][i] = grs * ur + gss * us + gst * ut;
+      wt[k] = grt * ur + gst * us + gtt * ut;
+    }
+  }
+  __syncthreads();
+
+  double dsum = 0.0;
+  if (active) {
+    T* out = a.Au + e * NP3 + ij;
+    const T* Bp = a.B ? a.B + e * NP3 + ij : nullptr;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      T au = 0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        au += DrT[q] * s_wr[elc][k][j][q];
+        au += DsT[q] * s_ws[elc][k][q][i];
+        au += Dg[q * NP + k] * wt[q];
+      }
+      if (Bp) au += (T)a.lambda * Bp[k * NP2] * uk[k];
+      out[k * NP2] = au;
+      dsum += (double)uk[k] * (double)au;
+    }
+  }
+  if (a.partial) {
+    double s = block_sum<C::THREADS>(dsum, s_red);
+    if (tid == 0) a.partial[lb] = s;
+  }
+}
+
+int ax_blocks(int N, int64_t ne) {
+  int epb = 1;
+  switch (N) {
+#define SEM_EPB_CASE(n) case n: epb = AxCfg<n>::EPB; break;
+    SEM_EPB_CASE(1) SEM_EPB_CASE(2) SEM_EPB_CASE(3) SEM_EPB_CASE(4) SEM_EPB_CASE(5)
+    SEM_EPB_CASE(6) SEM_EPB_CASE(7) SEM_EPB_CASE(8) SEM_EPB_CASE(9) SEM_EPB_CASE(10)
+    SEM_EPB_CASE(11) SEM_EPB_CASE(12) SEM_EPB_CASE(13) SEM_EPB_CASE(14) SEM_EPB_CASE(15)
+#undef SEM_EPB_CASE
+    default: break;
+  }
+  return (int)((ne + epb - 1) / epb);
+}
+
+template <typename T>
+void launch_ax(int N, const Table<AxArgs<T>>& t, int64_t total_blocks, const T* D, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  switch (N) {
+#define SEM_AX_CASE(n)                                                                        \
+  case n:                                                                                     \
+    hipLaunchKernelGGL((k_ax<n, T>), dim3((unsigned)total_blocks), dim3(AxCfg<n>::THREADS), 0, s, t, D); \
+    break;
+    SEM_AX_CASE(1) SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5)
+    SEM_AX_CASE(6) SEM_AX_CASE(7) SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10)
+    SEM_AX_CASE(11) SEM_AX_CASE(12) SEM_AX_CASE(13) SEM_AX_CASE(14) SEM_AX_CASE(15)
+#undef SEM_AX_CASE
+    default:
+      fail(SEM_EINVAL, "Ax: unsupported order N=%d", N);
+  }
+  SEM_HIP(hipGetLastError());
+}
+template void launch_ax<double>(int, const Table<AxArgs<double>>&, int64_t, const double*, hipStream_t);
+template void launch_ax<float>(int, const Table<AxArgs<float>>&, int64_t, const float*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// gather-scatter
+// ---------------------------------------------------------------------------
+constexpr int kGsThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kGsThreads) void k_gs(Table<GsArgs<T>> tab) {
+  int lb;
+  const GsArgs<T> a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  const int64_t t = (int64_t)lb * kGsThreads + threadIdx.x;
+  if (t < a.n_shared) {
+    const int q0 = a.off[t], q1 = a.off[t + 1];
+    if (a.mask && a.sdir[t]) {
+      for (int q = q0; q < q1; ++q) a.v[a.idx[q]] = T(0);
+    } else {
+      T sum = 0;
+      for (int q = q0; q < q1; ++q) sum += a.v[a.idx[q]];
+      for (int q = q0; q < q1; ++q) a.v[a.idx[q]] = sum;
+    }
+  } else if (a.mask) {
+    const int64_t d = t - a.n_shared;
+    if (d < a.n_dir) a.v[a.dir_idx[d]] = T(0);
+  }
+}
+
+int64_t gs_blocks(int64_t n_shared, int64_t n_dir) {
+  return (n_shared + n_dir + kGsThreads - 1) / kGsThreads;
+}
+
+template <typename T>
+void launch_gs(const Table<GsArgs<T>>& t, int64_t total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL((k_gs<T>), dim3((unsigned)total_blocks), dim3(kGsThreads), 0, s, t);
+  SEM_HIP(hipGetLastError());
+}
+template void launch_gs<double>(const Table<GsArgs<double>>&, int64_t, hipStream_t);
+template void launch_gs<float>(const Table<GsArgs<float>>&, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// vector updates
+// ---------------------------------------------------------------------------
+constexpr int kVecThreads = 256;
+constexpr int kVecPer = 8;
+constexpr int kVecChunk = kVecThreads * kVecPer;
+
+int64_t vec_blocks(int64_t n) { return (n + kVecChunk - 1) / kVecChunk; }
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
+  __shared__ double s_red[2][kVecThreads / 64];
+  int lb;
+  const VecArgs<T> a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  const int64_t base = (int64_t)lb * kVecChunk + threadIdx.x;
+  double acc0 = 0.0, acc1 = 0.0;
+  T alpha = 0, beta = 0, scale = 0;
+  if constexpr (OP == V_PCG_UPDATE) alpha = (T)a.scal[S_ALPHA];
+  if constexpr (OP == V_P_JACOBI || OP == V_P_FLEX) beta = (T)a.scal[S_BETA];
+  if constexpr (OP == V_NORMALIZE) scale = (T)a.scal[S_TMP];
+  const T c0 = (T)a.c0, c1 = (T)a.c1, c2 = (T)a.c2;
+#pragma unroll
+  for (int q = 0; q < kVecPer; ++q) {
+    const int64_t l = base + (int64_t)q * kVecThreads;
+    if (l >= a.n) break;
+    if constexpr (OP == V_PCG_UPDATE) {
+      a.x[l] += alpha * a.p[l];
+      const T rn = a.r[l] - alpha * a.w[l];
+      a.r[l] = rn;
+      if (a.owner[l]) {
+        acc0 += (double)rn * (double)rn;
+        if (a.dinv) acc1 += (double)rn * (double)a.dinv[l] * (double)rn;
+      }
+    } else if constexpr (OP == V_P_JACOBI) {
+      a.p[l] = a.dinv[l] * a.r[l] + beta * a.p[l];
+    } else if constexpr (OP == V_P_FLEX) {
+      a.p[l] = a.z[l] + beta * a.p[l];
+    } else if constexpr (OP == V_DOT2) {
+      if (a.owner[l]) {
+        const double zl = (double)a.z[l];
+        acc0 += zl * (double)a.w[l];
+        acc1 += zl * (double)a.r[l];
+      }
+    } else if constexpr (OP == V_DOT1) {
+      if (a.owner[l]) acc0 += (double)a.r[l] * (double)a.r[l];
+    } else if constexpr (OP == V_RZ_JACOBI) {
+      const T pz = a.dinv[l] * a.r[l];
+      a.p[l] = pz;
+      if (a.owner[l]) acc0 += (double)a.r[l] * (double)pz;
+    } else if constexpr (OP == V_CHEB_INIT0) {
+      const T d = c0 * a.dinv[l] * a.r[l];
+      a.d[l] = d;
+      a.x[l] = d;
+    } else if constexpr (OP == V_CHEB_INITX) {
+      const T res = a.r[l] - a.t[l];
+      a.res[l] = res;
+      const T d = c0 * a.dinv[l] * res;
+      a.d[l] = d;
+      a.x[l] += d;
+    } else if constexpr (OP == V_CHEB_STEP0) {
+      const T res = a.r[l] - a.t[l];
+      a.res[l] = res;
+      const T d = c1 * a.d[l] + c2 * a.dinv[l] * res;
+      a.d[l] = d;
+      a.x[l] += d;
+    } else if constexpr (OP == V_CHEB_STEP) {
+      const T res = a.res[l] - a.t[l];
+      a.res[l] = res;
+      const T d = c1 * a.d[l] + c2 * a.dinv[l] * res;
+      a.d[l] = d;
+      a.x[l] += d;
+    } else if constexpr (OP == V_ZERO) {
+      a.x[l] = T(0);
+    } else if constexpr (OP == V_COPY) {
+      a.x[l] = a.r[l];
+    } else if constexpr (OP == V_SCALE_DINV) {
+      a.x[l] = a.dinv[l] * a.r[l];
+    } else if constexpr (OP == V_NORMALIZE) {
+      a.x[l] = a.r[l] * scale;
+    } else if constexpr (OP == V_TRUE_RES) {
+      if (a.owner[l]) {
+        const double e = (double)a.r[l] - (double)a.t[l];
+        acc0 += e * e;
+      }
+    } else if constexpr (OP == V_DIV_DINV) {
+      a.x[l] = a.dinv[l] != T(0) ? a.r[l] / a.dinv[l] : T(0);
+    } else if constexpr (OP == V_SCALE) {
+      a.x[l] = c0 * a.r[l];
+    }
+  }
+  constexpr bool RED = (OP == V_PCG_UPDATE || OP == V_DOT2 || OP == V_DOT1 || OP == V_RZ_JACOBI ||
+                        OP == V_TRUE_RES);
+  if constexpr (RED) {
+    double s0 = wave_sum(acc0), s1 = wave_sum(acc1);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { s_red[0][wid] = s0; s_red[1][wid] = s1; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t0 = 0.0, t1 = 0.0;
+      for (int k = 0; k < kVecThreads / 64; ++k) { t0 += s_red[0][k]; t1 += s_red[1][k]; }
+      a.partial[lb] = t0;
+      a.partial[a.stride + lb] = t1;
+    }
+  }
+}
+
+template <typename T>
+void launch_vec(VecOp op, const Table<VecArgs<T>>& t, int64_t total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  const dim3 g((unsigned)total_blocks), b(kVecThreads);
+  switch (op) {
+#define SEM_VEC_CASE(o) case o: hipLaunchKernelGGL((k_vec<T, o>), g, b, 0, s, t); break;
+    SEM_VEC_CASE(V_PCG_UPDATE) SEM_VEC_CASE(V_P_JACOBI) SEM_VEC_CASE(V_P_FLEX)
+    SEM_VEC_CASE(V_DOT2) SEM_VEC_CASE(V_DOT1) SEM_VEC_CASE(V_RZ_JACOBI)
+    SEM_VEC_CASE(V_CHEB_INIT0) SEM_VEC_CASE(V_CHEB_INITX) SEM_VEC_CASE(V_CHEB_STEP0)
+    SEM_VEC_CASE(V_CHEB_STEP) SEM_VEC_CASE(V_ZERO) SEM_VEC_CASE(V_COPY)
+    SEM_VEC_CASE(V_SCALE_DINV) SEM_VEC_CASE(V_NORMALIZE) SEM_VEC_CASE(V_TRUE_RES)
+    SEM_VEC_CASE(V_DIV_DINV) SEM_VEC_CASE(V_SCALE)
+#undef SEM_VEC_CASE
+    default:
+      fail(SEM_EINVAL, "unknown vector op %d", (int)op);
+  }
+  SEM_HIP(hipGetLastError());
+}
+template void launch_vec<double>(VecOp, const Table<VecArgs<double>>&, int64_t, hipStream_t);
+template void launch_vec<float>(VecOp, const Table<VecArgs<float>>&, int64_t, hipStream_t);
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kVecThreads) void k_cast(Table<CastArgs<Tin, Tout>> tab) {
+  int lb;
+  const CastArgs<Tin, Tout> a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  const int64_t base = (int64_t)lb * kVecChunk + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kVecPer; ++q) {
+    const int64_t l = base + (int64_t)q * kVecThreads;
+    if (l < a.n) a.out[l] = (Tout)a.in[l];
+  }
+}
+
+template <typename Tin, typename Tout>
+void launch_cast(const Table<CastArgs<Tin, Tout>>& t, int64_t total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3((unsigned)total_blocks), dim3(kVecThreads), 0, s, t);
+  SEM_HIP(hipGetLastError());
+}
+template void launch_cast<double, float>(const Table<CastArgs<double, float>>&, int64_t, hipStream_t);
+template void launch_cast<float, double>(const Table<CastArgs<float, double>>&, int64_t, hipStream_t);
+template void launch_cast<double, double>(const Table<CastArgs<double, double>>&, int64_t, hipStream_t);
+template void launch_cast<float, float>(const Table<CastArgs<float, float>>&, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// finalize: per-problem fixed-order reduction + scalar recurrences
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFinThreads) void k_fin(Table<FinArgs> tab, int op) {
+  __shared__ double s_red[2][kFinThreads];
+  const FinArgs a = tab.many ? tab.many[blockIdx.x] : tab.one;
+  if (skipped(a.skip)) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t k = threadIdx.x; k < a.nblk; k += kFinThreads) {
+    s0 += a.partial[k];
+    s1 += a.partial[a.stride + k];
+  }
+  s_red[0][threadIdx.x] = s0;
+  s_red[1][threadIdx.x] = s1;
+  __syncthreads();
+  for (int w = kFinThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s_red[0][threadIdx.x] += s_red[0][threadIdx.x + w];
+      s_red[1][threadIdx.x] += s_red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  s0 = s_red[0][0];
+  s1 = s_red[1][0];
+  double* sc = a.scal;
+  int* fl = a.flags;
+  switch (op) {
+    case FIN_INIT:
+      sc[S_BB] = s0;
+      sc[S_RR] = s0;
+      sc[S_BETA] = 0.0;
+      sc[S_ALPHA] = 0.0;
+      sc[S_RZ] = 0.0;
+      fl[F_ITERS] = 0;
+      fl[F_STATUS] = 1;
+      fl[F_DONE] = 0;
+      if (!isfinite(s0)) { fl[F_STATUS] = SEM_ENAN; fl[F_DONE] = 1; sc[S_RELRES] = s0; }
+      else if (s0 == 0.0) { fl[F_STATUS] = SEM_OK; fl[F_DONE] = 1; sc[S_RELRES] = 0.0; }
+      else sc[S_RELRES] = 1.0;
+      break;
+    case FIN_RZ:
+      sc[S_RZ] = s0;
+      sc[S_BETA] = 0.0;
+      if (!isfinite(s0)) { fl[F_STATUS] = SEM_ENAN; fl[F_DONE] = 1; }
+      break;
+    case FIN_ALPHA: {
+      sc[S_PW] = s0;
+      const double al = sc[S_RZ] / s0;
+      sc[S_ALPHA] = al;
+      if (!isfinite(al)) { fl[F_STATUS] = SEM_ENAN; fl[F_DONE] = 1; sc[S_ALPHA] = 0.0; }
+      break;
+    }
+    case FIN_CHECK:
+    case FIN_CHECK_JACOBI: {
+      sc[S_RR] = s0;
+      const int it = ++fl[F_ITERS];
+      if (a.total) ++(*a.total);
+      const double rel = sqrt(s0 / sc[S_BB]);
+      sc[S_RELRES] = rel;
+      if (!isfinite(s0)) { fl[F_STATUS] = SEM_ENAN; fl[F_DONE] = 1; }
+      else if (a.fixed > 0) { if (it >= a.fixed) { fl[F_STATUS] = SEM_OK; fl[F_DONE] = 1; } }
+      else if (rel <= a.rtol) { fl[F_STATUS] = SEM_OK; fl[F_DONE] = 1; }
+      else if (it >= a.maxit) { fl[F_STATUS] = SEM_ENOCONV; fl[F_DONE] = 1; }
+      if (op == FIN_CHECK_JACOBI && !fl[F_DONE]) {
+        sc[S_BETA] = s1 / sc[S_RZ];
+        sc[S_RZ] = s1;
+      }
+      break;
+    }
+    case FIN_BETA_FLEX:
+      // (z_new, r_new - r_old) = -alpha (z_new, w) since r_new = r_old - alpha w
+      sc[S_ZW] = s0;
+      sc[S_RZ_NEW] = s1;
+      sc[S_BETA] = fl[F_ITERS] == 0 ? 0.0 : -sc[S_ALPHA] * s0 / sc[S_RZ];
+      sc[S_RZ] = s1;
+      if (!isfinite(sc[S_BETA])) { fl[F_STATUS] = SEM_ENAN; fl[F_DONE] = 1; }
+      break;
+    case FIN_NORM:
+      sc[S_TMP] = 1.0 / sqrt(s0);
+      break;
+    case FIN_STORE:
+      sc[S_TMP] = s0;
+      break;
+    default:
+      break;
+  }
+}
+
+void launch_fin(FinOp op, const Table<FinArgs>& t, int nprob, hipStream_t s) {
+  if (nprob <= 0) return;
+  hipLaunchKernelGGL(k_fin, dim3(nprob), dim3(kFinThreads), 0, s, t, (int)op);
+  SEM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// pMG transfers: out = (M x M x M) in per element, M is NO x NI
+// ---------------------------------------------------------------------------
+constexpr int kXferThreads = 256;
+
+template <int NI, int NO>
+struct XferCfg {
+  static constexpr int MAXC = (NI * NI * NI > NO * NO * NO) ? NI * NI * NI : NO * NO * NO;
+  static constexpr int EPB = (kXferThreads / MAXC) > 0 ? (kXferThreads / MAXC) : 1;
+  static constexpr int S0 = NI * NI * NI, S1 = NI * NI * NO, S2 = NI * NO * NO, S3 = NO * NO * NO;
+};
+
+// sum-factorised tensor apply on EPB elements staged in LDS
+template <int NI, int NO, typename T>
+__device__ __forceinline__ void tensor3(const T* sM, T (*s0)[XferCfg<NI, NO>::S0],
+                                        T (*s1)[XferCfg<NI, NO>::S1], T (*s2)[XferCfg<NI, NO>::S2],
+                                        T (*s3)[XferCfg<NI, NO>::S3]) {
+  using C = XferCfg<NI, NO>;
+  // along i: s1[k][j][a] = sum_i M[a][i] s0[k][j][i]
+  for (int t = threadIdx.x; t < C::EPB * C::S1; t += kXferThreads) {
+    const int el = t / C::S1, r = t - el * C::S1;
+    const int aa = r % NO, kj = r / NO;
+    T acc = 0;
+#pragma unroll
+    for (int q = 0; q < NI; ++q) acc += sM[aa * NI + q] * s0[el][kj * NI + q];
+    s1[el][r] = acc;
+  }
+  __syncthreads();
+  // along j: s2[k][b][a] = sum_j M[b][j] s1[k][j][a]
+  for (int t = threadIdx.x; t < C::EPB * C::S2; t += kXferThreads) {
+    const int el = t / C::S2, r = t - el * C::S2;
+    const int aa = r % NO, bb = (r / NO) % NO, k = r / (NO * NO);
+    T acc = 0;
+#pragma unroll
+    for (int q = 0; q < NI; ++q) acc += sM[bb * NI + q] * s1[el][(k * NI + q) * NO + aa];
+    s2[el][r] = acc;
+  }
+  __syncthreads();
+  // along k: s3[c][b][a] = sum_k M[c][k] s2[k][b][a]
+  for (int t = threadIdx.x; t < C::EPB * C::S3; t += kXferThreads) {
+    const int el = t / C::S3, r = t - el * C::S3;
+    const int ba = r % (NO * NO), c = r / (NO * NO);
+    T acc = 0;
+#pragma unroll
+    for (int q = 0; q < NI; ++q) acc += sM[c * NI + q] * s2[el][q * NO * NO + ba];
+    s3[el][r] = acc;
+  }
+  __syncthreads();
+}
+
+// DIR 0: prolong (NI = coarse, NO = fine): xf += M zc
+// DIR 1: restrict (NI = fine, NO = coarse): out_c = M ((rf - tf) . owner)
+template <int NI, int NO, typename Tf, typename Tc, int DIR>
+__global__ __launch_bounds__(kXferThreads) void k_xfer(Table<XferArgs<Tf, Tc>> tab, const double* __restrict__ Mg) {
+  using C = XferCfg<NI, NO>;
+  __shared__ Tf sM[NO * NI];
+  __shared__ Tf s0[C::EPB][C::S0];
+  __shared__ Tf s1[C::EPB][C::S1];
+  __shared__ Tf s2[C::EPB][C::S2];
+  __shared__ Tf s3[C::EPB][C::S3];
+  int lb;
+  const XferArgs<Tf, Tc> a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  const int64_t e_first = (int64_t)lb * C::EPB;
+  for (int t = threadIdx.x; t < NO * NI; t += kXferThreads) sM[t] = (Tf)Mg[t];
+  for (int t = threadIdx.x; t < C::EPB * C::S0; t += kXferThreads) {
+    const int el = t / C::S0, r = t - el * C::S0;
+    const int64_t e = e_first + el;
+    Tf v = 0;
+    if (e < a.E) {
+      const int64_t g = e * C::S0 + r;
+      if constexpr (DIR == 0) {
+        v = (Tf)a.zc[g];
+      } else {
+        v = a.rf[g];
+        if (a.tf) v -= a.tf[g];
+        if (!a.owner_f[g]) v = 0;
+      }
+    }
+    s0[el][r] = v;
+  }
+  __syncthreads();
+  tensor3<NI, NO, Tf>(sM, s0, s1, s2, s3);
+  for (int t = threadIdx.x; t < C::EPB * C::S3; t += kXferThreads) {
+    const int el = t / C::S3, r = t - el * C::S3;
+    const int64_t e = e_first + el;
+    if (e >= a.E) continue;
+    const int64_t g = e * C::S3 + r;
+    if constexpr (DIR == 0) a.xf[g] += s3[el][r];
+    else a.out_c[g] = (Tc)s3[el][r];
+  }
+}
+
+template <int NI, int NO>
+static int xfer_epb() { return XferCfg<NI, NO>::EPB; }
+
+// supported level pairs (fine, coarse) with coarse < fine <= 15
+// (the default schedules {N, (N-1)/2, 1}, every N -> 1, and the paper's
+// 8-5-1 and 8-6-4-1 schedules)
+#define SEM_FOR_PAIRS(X)                                                                      \
+  X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(9, 1) X(10, 1) X(11, 1) X(12, 1)    \
+  X(13, 1) X(14, 1) X(15, 1) X(5, 2) X(6, 2) X(7, 3) X(8, 3) X(9, 4) X(10, 4) X(11, 5)         \
+  X(12, 5) X(13, 6) X(14, 6) X(15, 7) X(8, 5) X(8, 6) X(6, 4) X(7, 5) X(5, 3) X(9, 5) X(9, 7)
+
+int xfer_blocks(int Nf, int Nc, int64_t E) {
+  int epb = 0;
+#define SEM_XB(f, c) if (Nf == f && Nc == c) epb = xfer_epb<c + 1, f + 1>();
+  SEM_FOR_PAIRS(SEM_XB)
+#undef SEM_XB
+  if (epb == 0) fail(SEM_EINVAL, "pMG transfer %d->%d not supported", Nf, Nc);
+  return (int)((E + epb - 1) / epb);
+}
+
+template <typename Tf, typename Tc>
+void launch_xfer(int dir, int Nf, int Nc, const Table<XferArgs<Tf, Tc>>& t, int64_t total_blocks,
+                 const double* M, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  bool done = false;
+#define SEM_XL(f, c)                                                                                    \
+  if (!done && Nf == f && Nc == c) {                                                                    \
+    done = true;                                                                                        \
+    if (dir == 0)                                                                                       \
+      hipLaunchKernelGGL((k_xfer<c + 1, f + 1, Tf, Tc, 0>), dim3((unsigned)total_blocks), dim3(kXferThreads), 0, s, t, M); \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_xfer<f + 1, c + 1, Tf, Tc, 1>), dim3((unsigned)total_blocks), dim3(kXferThreads), 0, s, t, M); \
+  }
+  SEM_FOR_PAIRS(SEM_XL)
+#undef SEM_XL
+  if (!done) fail(SEM_EINVAL, "pMG transfer %d->%d not supported", Nf, Nc);
+  SEM_HIP(hipGetLastError());
+}
+template void launch_xfer<float, float>(int, int, int, const Table<XferArgs<float, float>>&, int64_t, const double*, hipStream_t);
+template void launch_xfer<float, double>(int, int, int, const Table<XferArgs<float, double>>&, int64_t, const double*, hipStream_t);
+template void launch_xfer<double, double>(int, int, int, const Table<XferArgs<double, double>>&, int64_t, const double*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+
+// Geometric factors at every GLL point (one thread per point).
+// Jm[l][m] = d x_l / d r_m by Dhat along i, j, k; cof_m = det * grad r_m;
+// G_mn = W cof_m . cof_n / det; B = W det.
+constexpr int kGeoThreads = 256;
+
+__global__ __launch_bounds__(kGeoThreads) void k_geometry(int N, int64_t nloc, const double* __restrict__ X,
+                                                          const double* __restrict__ Y, const double* __restrict__ Z,
+                                                          const double* __restrict__ Dg, const double* __restrict__ wg,
+                                                          double* G64, float* G32, double* B64, float* B32,
+                                                          double* detmin_partial, double* vol_partial,
+                                                          unsigned long long* bad) {
+  __shared__ double s_min[kGeoThreads / 64], s_vol[kGeoThreads / 64];
+  const int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
+  const int64_t l = (int64_t)blockIdx.x * kGeoThreads + threadIdx.x;
+  double detv = INFINITY, volv = 0.0;
+  if (l < nloc) {
+    const int64_t e = l / NP3;
+    const int p = (int)(l - e * NP3);
+    const int i = p % NP, j = (p / NP) % NP, k = p / NP2;
+    const double* xs[3] = {X + e * NP3, Y + e * NP3, Z + e * NP3};
+    double Jm[3][3];
+    for (int c = 0; c < 3; ++c) {
+      double dr = 0, ds = 0, dt = 0;
+      for (int q = 0; q < NP; ++q) {
+        dr += Dg[i * NP + q] * xs[c][k * NP2 + j * NP + q];
+        ds += Dg[j * NP + q] * xs[c][k * NP2 + q * NP + i];
+        dt += Dg[k * NP + q] * xs[c][q * NP2 + j * NP + i];
+      }
+      Jm[c][0] = dr;
+      Jm[c][1] = ds;
+      Jm[c][2] = dt;
+    }
+    const double xr = Jm[0][0], xs_ = Jm[0][1], xt = Jm[0][2];
+    const double yr = Jm[1][0], ys = Jm[1][1], yt = Jm[1][2];
+    const double zr = Jm[2][0], zs = Jm[2][1], zt = Jm[2][2];
+    // cofactor rows: cof_m[l] = det * d r_m / d x_l
+    const double a0[3] = {ys * zt - yt * zs, xt * zs - xs_ * zt, xs_ * yt - xt * ys};
+    const double a1[3] = {yt * zr - yr * zt, xr * zt - xt * zr, xt * yr - xr * yt};
+    const double a2[3] = {yr * zs - ys * zr, xs_ * zr - xr * zs, xr * ys - xs_ * yr};
+    const double det = xr * a0[0] + yr * a0[1] + zr * a0[2];
+    const double W = wg[i] * wg[j] * wg[k];
+    if (!(det > 0.0)) atomicMin(bad, (unsigned long long)l);
+    const double f = W / det;
+    const double g[6] = {f * (a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2]),
+                         f * (a0[0] * a1[0] + a0[1] * a1[1] + a0[2] * a1[2]),
+                         f * (a0[0] * a2[0] + a0[1] * a2[1] + a0[2] * a2[2]),
+                         f * (a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2]),
+                         f * (a1[0] * a2[0] + a1[1] * a2[1] + a1[2] * a2[2]),
+                         f * (a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2])};
+    for (int c = 0; c < 6; ++c) {
+      G64[(e * 6 + c) * NP3 + p] = g[c];
+      G32[(e * 6 + c) * NP3 + p] = (float)g[c];
+    }
+    B64[l] = W * det;
+    B32[l] = (float)(W * det);
+    detv = det;
+    volv = W * det;
+  }
+  // fixed-order block reductions (min and sum)
+  double m = detv, v = volv;
+  for (int off = 32; off > 0; off >>= 1) {
+    m = fmin(m, __shfl_xor(m, off, 64));
+    v += __shfl_xor(v, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) { s_min[wid] = m; s_vol[wid] = v; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = s_min[0], vv = s_vol[0];
+    for (int k2 = 1; k2 < kGeoThreads / 64; ++k2) { mm = fmin(mm, s_min[k2]); vv += s_vol[k2]; }
+    detmin_partial[blockIdx.x] = mm;
+    vol_partial[blockIdx.x] = vv;
+  }
+}
+
+void launch_geometry(const MeshData& m, double* detmin_partial, double* vol_partial, int64_t* bad_index,
+                     hipStream_t s) {
+  const int64_t nb = (m.nloc + kGeoThreads - 1) / kGeoThreads;
+  hipLaunchKernelGGL(k_geometry, dim3((unsigned)nb), dim3(kGeoThreads), 0, s, m.N, m.nloc,
+                     m.x.as<double>(), m.y.as<double>(), m.z.as<double>(), m.Dg64.as<double>(),
+                     m.wg.as<double>(), m.G64.as<double>(), m.G32.as<float>(), m.B64.as<double>(),
+                     m.B32.as<float>(), detmin_partial, vol_partial, (unsigned long long*)bad_index);
+  SEM_HIP(hipGetLastError());
+}
+
+// Local diagonal of A^e = sum_mn D_m^T diag(G_mn) D_n at (i,j,k).
+__global__ __launch_bounds__(256) void k_diag(int N, int64_t nloc, const double* __restrict__ G,
+                                              const double* __restrict__ Dg, double* dl) {
+  const int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
+  const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (l >= nloc) return;
+  const int64_t e = l / NP3;
+  const int p = (int)(l - e * NP3);
+  const int i = p % NP, j = (p / NP) % NP, k = p / NP2;
+  const double* g = G + e * 6 * NP3;
+  double d = 0.0;
+  for (int q = 0; q < NP; ++q) {
+    const double a = Dg[q * NP + i], b = Dg[q * NP + j], c = Dg[q * NP + k];
+    d += a * a * g[0 * NP3 + k * NP2 + j * NP + q];
+    d += b * b * g[3 * NP3 + k * NP2 + q * NP + i];
+    d += c * c * g[5 * NP3 + q * NP2 + j * NP + i];
+  }
+  const double di = Dg[i * NP + i], dj = Dg[j * NP + j], dk = Dg[k * NP + k];
+  d += 2.0 * di * dj * g[1 * NP3 + p] + 2.0 * di * dk * g[2 * NP3 + p] + 2.0 * dj * dk * g[4 * NP3 + p];
+  dl[l] = d;
+}
+
+void launch_diag_local(const MeshData& m, double* dl, hipStream_t s) {
+  const int64_t nb = (m.nloc + 255) / 256;
+  hipLaunchKernelGGL(k_diag, dim3((unsigned)nb), dim3(256), 0, s, m.N, m.nloc, m.G64.as<double>(),
+                     m.Dg64.as<double>(), dl);
+  SEM_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void k_dinv(int64_t nloc, const double* __restrict__ d,
+                                              const uint8_t* __restrict__ dmask, double* inv64, float* inv32) {
+  const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (l >= nloc) return;
+  const double v = dmask[l] ? 0.0 : 1.0 / d[l];
+  inv64[l] = v;
+  inv32[l] = (float)v;
+}
+
+void launch_dinv_finish(const MeshData& m, const double* d_assembled, hipStream_t s) {
+  const int64_t nb = (m.nloc + 255) / 256;
+  hipLaunchKernelGGL(k_dinv, dim3((unsigned)nb), dim3(256), 0, s, m.nloc, d_assembled, m.dmask.as<uint8_t>(),
+                     m.dinv64.as<double>(), m.dinv32.as<float>());
+  SEM_HIP(hipGetLastError());
+}
+
+// out[e] = (M x M x M) in[e], M is (Nc+1) x (Nf+1): coarse nodal coordinates
+// as the fine isoparametric map evaluated at the coarse GLL points.
+__global__ __launch_bounds__(256) void k_tensor_coords(int NI, int NO, int64_t E, const double* __restrict__ in,
+                                                       double* out, const double* __restrict__ M) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int NO3 = NO * NO * NO, NI3 = NI * NI * NI;
+  if (t >= E * NO3) return;
+  const int64_t e = t / NO3;
+  const int r = (int)(t - e * NO3);
+  const int a = r % NO, b = (r / NO) % NO, c = r / (NO * NO);
+  const double* u = in + e * NI3;
+  double acc = 0.0;
+  for (int k = 0; k < NI; ++k)
+    for (int j = 0; j < NI; ++j) {
+      double row = 0.0;
+      for (int i = 0; i < NI; ++i) row += M[a * NI + i] * u[(k * NI + j) * NI + i];
+      acc += M[c * NI + k] * M[b * NI + j] * row;
+    }
+  out[t] = acc;
+}
+
+void launch_tensor_coords(int Nf, int Nc, int64_t E, const double* in, double* out, const double* Mcf,
+                          hipStream_t s) {
+  const int NO3 = (Nc + 1) * (Nc + 1) * (Nc + 1);
+  const int64_t nb = (E * NO3 + 255) / 256;
+  hipLaunchKernelGGL(k_tensor_coords, dim3((unsigned)nb), dim3(256), 0, s, Nf + 1, Nc + 1, E, in, out, Mcf);
+  SEM_HIP(hipGetLastError());
+}
+
+// splitmix64 (Steele, Lea & Flood 2014) keyed by global ID -> [-1, 1), 0 on Dirichlet copies
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_start(int64_t n, const int64_t* __restrict__ gid,
+                                               const uint8_t* __restrict__ dmask, double* v) {
+  const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (l >= n) return;
+  const double u = (double)(splitmix64((uint64_t)gid[l]) >> 11) * 0x1.0p-53;
+  v[l] = dmask[l] ? 0.0 : 2.0 * u - 1.0;
+}
+
+void launch_start_vector(int64_t n, const int64_t* gid, const uint8_t* dmask, double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_start, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, gid, dmask, v);
+  SEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mass(int64_t n, const T* __restrict__ B, const T* __restrict__ u, T* Bu) {
+  const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (l < n) Bu[l] = B[l] * u[l];
+}
+
+void launch_mass(int N, int64_t nloc, int is_f32, const void* B, const void* u, void* Bu, hipStream_t s) {
+  (void)N;
+  const dim3 g((unsigned)((nloc + 255) / 256)), b(256);
+  if (is_f32)
+    hipLaunchKernelGGL(k_mass<float>, g, b, 0, s, nloc, (const float*)B, (const float*)u, (float*)Bu);
+  else
+    hipLaunchKernelGGL(k_mass<double>, g, b, 0, s, nloc, (const double*)B, (const double*)u, (double*)Bu);
+  SEM_HIP(hipGetLastError());
+}
+
+}  // namespace sem

@@ -1,0 +1,181 @@
+"""GPU parity of the element operators through the C ABI: geometric factors,
+Ax (FP64 and FP32), gather-scatter, mask, mass, Helmholtz, dot products and
+the Jacobi diagonal, against the FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from paper_2110_01716_amd import workloads as wl
+
+from gpu_util import dev, host, oracle_setup, print_case, rel_err
+
+pytestmark = pytest.mark.gpu
+
+# (nx, ny, nz, N): several tiles and ragged tails (E not a multiple of the
+# elements-per-block of the Ax kernel)
+CASES = [(3, 4, 5, 1), (3, 3, 2, 2), (2, 3, 5, 3), (3, 2, 3, 4), (2, 3, 3, 5), (3, 3, 3, 7), (2, 2, 3, 9),
+         (2, 2, 2, 12), (1, 1, 2, 15)]
+
+
+@pytest.fixture(scope="module")
+def sem():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_2110_01716_amd import sem as s
+    s.load()
+    return s
+
+
+def _mesh(sem, nx, ny, nz, N, seed=1, deform=0.05):
+    bm = wl.box_mesh(nx, ny, nz, N=N, deform=deform, seed=seed)
+    return bm, sem.Mesh.from_box(bm)
+
+
+@pytest.mark.parametrize("nx,ny,nz,N", CASES)
+def test_geometry_and_diagonal(sem, nx, ny, nz, N):
+    import torch
+    print_case("geometry", nx, ny, nz, N)
+    bm, m = _mesh(sem, nx, ny, nz, N)
+    G, B, detJ = oracle_setup(bm)
+    Gd = torch.empty((bm.E, 6, bm.Np), dtype=torch.float64, device="cuda")
+    Bd = torch.empty((bm.E, bm.Np), dtype=torch.float64, device="cuda")
+    Dd = torch.empty((bm.E, bm.Np), dtype=torch.float64, device="cuda")
+    sem.sem_mesh_export(m.h, Gd, Bd, Dd)
+    assert rel_err(host(Gd), G) <= 1e-12
+    assert rel_err(host(Bd), B) <= 1e-13
+    dinv = ops.jacobi_inverse(N, G, bm.gid, bm.dirichlet)
+    assert rel_err(host(Dd), dinv) <= 1e-12
+    info = m.info()
+    assert info["n_unique"] == len(np.unique(bm.gid))
+    assert abs(info["min_detJ"] - detJ.min()) <= 1e-12 * detJ.max()
+    assert abs(info["volume"] - B.sum()) <= 1e-12 * B.sum()
+    assert info["n_interior"] == (nx * N - 1) * (ny * N - 1) * (nz * N - 1)
+
+
+@pytest.mark.parametrize("nx,ny,nz,N", CASES)
+def test_ax_fp64(sem, nx, ny, nz, N):
+    import torch
+    print_case("ax64", nx, ny, nz, N)
+    bm, m = _mesh(sem, nx, ny, nz, N)
+    G, _, _ = oracle_setup(bm)
+    u = np.random.default_rng(N).uniform(-1, 1, bm.x.shape)
+    ref = ops.ax_local(N, G, u)
+    ud = dev(u)
+    Ad = torch.full_like(ud, np.nan)
+    sem.sem_ax(m.h, ud, Ad)
+    assert rel_err(host(Ad), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("nx,ny,nz,N", [(3, 3, 3, 7), (2, 3, 5, 3), (3, 4, 5, 1), (2, 2, 3, 9)])
+def test_ax_fp32(sem, nx, ny, nz, N):
+    import torch
+    print_case("ax32", nx, ny, nz, N)
+    bm, m = _mesh(sem, nx, ny, nz, N)
+    G, _, _ = oracle_setup(bm)
+    u = np.random.default_rng(N).uniform(-1, 1, bm.x.shape)
+    ref = ops.ax_local(N, G, u)
+    ud = dev(u, torch.float32)
+    Ad = torch.zeros_like(ud)
+    sem.sem_ax(m.h, ud, Ad)
+    assert rel_err(host(Ad), ref) <= 2e-5
+
+
+def test_ax_element_range_leaves_others(sem):
+    import torch
+    print_case("ax-range")
+    bm, m = _mesh(sem, 3, 3, 3, 7)
+    G, _, _ = oracle_setup(bm)
+    u = np.random.default_rng(5).uniform(-1, 1, bm.x.shape)
+    ref = ops.ax_local(7, G, u)
+    ud = dev(u)
+    Ad = torch.full_like(ud, 7.0)
+    sem.sem_ax(m.h, ud, Ad, e0=5, ne=11)
+    out = host(Ad)
+    assert rel_err(out[5:16], ref[5:16]) <= 1e-12
+    assert np.all(out[:5] == 7.0) and np.all(out[16:] == 7.0)
+    with pytest.raises(sem.SemError):
+        sem.sem_ax(m.h, ud, Ad, e0=20, ne=10)
+
+
+@pytest.mark.parametrize("N", [1, 3, 7])
+def test_gather_scatter_and_mask(sem, N):
+    import torch
+    print_case("gs", N)
+    bm, m = _mesh(sem, 3, 4, 2, N)
+    v = np.random.default_rng(3).uniform(-1, 1, bm.x.shape)
+    ref = ops.gs(bm.gid, v)
+    for mask in (False, True):
+        vd = dev(v)
+        sem.sem_gs(m.h, vd, apply_mask=mask)
+        exp = ops.mask(bm.dirichlet, ref) if mask else ref
+        assert rel_err(host(vd), exp) <= 1e-14
+    # FP32
+    vd = dev(v, torch.float32)
+    sem.sem_gs(m.h, vd, apply_mask=True)
+    assert rel_err(host(vd), ops.mask(bm.dirichlet, ref)) <= 1e-6
+    # multiplicity
+    one = torch.ones((bm.E, bm.Np), dtype=torch.float64, device="cuda")
+    sem.sem_gs(m.h, one, apply_mask=False)
+    np.testing.assert_array_equal(host(one), ops.multiplicity(bm.gid))
+
+
+def test_gather_scatter_random_relabelling(sem):
+    print_case("gs-relabel")
+    bm = wl.box_mesh(3, 3, 3, N=4, deform=0.05, seed=2)
+    rb = wl.relabel(bm, 11)
+    m = sem.Mesh.from_box(rb)
+    v = np.random.default_rng(4).uniform(-1, 1, rb.x.shape)
+    vd = dev(v)
+    sem.sem_gs(m.h, vd, apply_mask=True)
+    assert rel_err(host(vd), ops.mask(rb.dirichlet, ops.gs(rb.gid, v))) <= 1e-14
+    assert m.info()["n_unique"] == 13 ** 3
+
+
+def test_dot_mass_helmholtz(sem):
+    import torch
+    print_case("dot-mass")
+    bm, m = _mesh(sem, 2, 3, 4, 5)
+    G, B, _ = oracle_setup(bm)
+    a = ops.gs(bm.gid, np.random.default_rng(1).uniform(-1, 1, bm.x.shape))
+    b = ops.gs(bm.gid, np.random.default_rng(2).uniform(-1, 1, bm.x.shape))
+    a = ops.mask(bm.dirichlet, a)
+    ad, bd = dev(a), dev(b)
+    d = sem.sem_dot(m.h, ad, bd)
+    # owners exclude Dirichlet copies: a is zero there, so this is the unique-DOF product
+    assert abs(d - ops.dot(bm.gid, a, b)) <= 1e-12 * abs(ops.dot(bm.gid, np.abs(a), np.abs(b)))
+    out = torch.empty_like(ad)
+    sem.sem_mass(m.h, ad, out)
+    assert rel_err(host(out), B * a) <= 1e-13
+    sem.sem_helmholtz(m.h, ad, out, 3.5)
+    assert rel_err(host(out), ops.helmholtz_local(5, G, B, 3.5, a)) <= 1e-12
+
+
+def test_mesh_errors(sem):
+    print_case("mesh-errors")
+    bm = wl.box_mesh(2, N=3)
+    # inverted element: mirror x inside element 0
+    bad = wl.box_mesh(2, N=3)
+    x = bad.x.copy()
+    x[0] = x[0].max() + x[0].min() - x[0]
+    with pytest.raises(sem.SemError) as ei:
+        sem.Mesh(3, x, bad.y, bad.z, bad.gid, bad.dirichlet)
+    assert ei.value.code in (sem.SEM_EGEOM, sem.SEM_EINVAL)
+    # inconsistent Dirichlet flags across copies of one ID
+    d = bm.dirichlet.copy()
+    d[0, 3] = 0  # (i=N, j=0, k=0): on the y=0 face, shared with element 1
+    with pytest.raises(sem.SemError) as ei:
+        sem.Mesh(3, bm.x, bm.y, bm.z, bm.gid, d)
+    assert ei.value.code == sem.SEM_EINVAL
+    # coordinates differing across copies
+    y = bm.y.copy()
+    y[1, 0] += 1e-6  # above the copy tolerance, small enough to keep det J > 0
+    with pytest.raises(sem.SemError) as ei:
+        sem.Mesh(3, bm.x, y, bm.z, bm.gid, bm.dirichlet)
+    assert ei.value.code == sem.SEM_EINVAL
+    # negative global ID
+    g = bm.gid.copy()
+    g[0, 5] = -3
+    with pytest.raises(sem.SemError) as ei:
+        sem.Mesh(3, bm.x, bm.y, bm.z, g, bm.dirichlet)
+    assert ei.value.code == sem.SEM_EINVAL
