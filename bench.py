@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--solve-c2", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter calibration under a profiler)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no multi-GPU path.",
@@ -142,6 +144,14 @@ def main():
     import torch
     from paper_2110_01716_amd import sem, workloads as wl
     sem.load()
+    if a.calib_copy:
+        src = torch.rand(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 1 GiB read + 1 GiB write")
+        del src, dst
     spec = dict(wl.config_meshes()["ax_64x64x64_N7"])
     spec["n"] = a.n
     bm, m = build_mesh(sem, spec)

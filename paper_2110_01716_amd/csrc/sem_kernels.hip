@@ -33,23 +33,55 @@ namespace sem {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+
+// Pointers that arrive inside argument structs are generic to the compiler,
+// which then emits flat loads (counted on both the vector-memory and LDS
+// counters, so every load waits before the next LDS access). All solver
+// buffers are global memory: say so.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SEM_GLOBAL __attribute__((address_space(1)))
+#else
+#define SEM_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ SEM_GLOBAL T* gl(T* p) { return (SEM_GLOBAL T*)p; }
+template <typename T>
+__device__ __forceinline__ const SEM_GLOBAL T* gl(const T* p) { return (const SEM_GLOBAL T*)p; }
+
 template <typename A>
 __device__ __forceinline__ A fetch_args(const Table<A>& t, int b, int& lb) {
   if (t.many == nullptr) {
     lb = b;
     return t.one;
   }
+  const SEM_GLOBAL int* st = gl(t.starts);
   int lo = 0, hi = t.n;
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
-    if (t.starts[mid] <= b) lo = mid; else hi = mid;
+    if (st[mid] <= b) lo = mid; else hi = mid;
   }
-  lb = b - t.starts[lo];
-  return t.many[lo];
+  lb = b - st[lo];
+  return gl(t.many)[lo];
 }
 
 __device__ __forceinline__ bool skipped(const Skip& s) {
-  return (s.f0 && *(volatile const int*)s.f0) || (s.f1 && *(volatile const int*)s.f1);
+  return (s.f0 && *(volatile const SEM_GLOBAL int*)gl(s.f0)) || (s.f1 && *(volatile const SEM_GLOBAL int*)gl(s.f1));
+}
+
+// Barrier for LDS hand-offs only: unlike __syncthreads() it does not wait for
+// outstanding global loads, so an element's geometric factors stay in flight
+// across it. A one-wave workgroup needs no hardware barrier at all.
+template <int THREADS>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (THREADS <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -89,7 +121,7 @@ struct AxCfg {
   static constexpr int NPAD = NP | 1;  // odd row stride: conflict-free column reads
 };
 
-template <int N, typename T>
+template <int N, typename T, bool HELM>
 __global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, const T* __restrict__ Dg) {
   using C = AxCfg<N>;
   constexpr int NP = C::NP, NP2 = C::NP2, NP3 = C::NP3, EPB = C::EPB, NPAD = C::NPAD;
@@ -111,29 +143,36 @@ __global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, 
   const int elc = el < EPB ? el : 0;
   const int64_t e = a.e0 + el_local;
 
+  const SEM_GLOBAL T* Dgl = gl(Dg);
   T Dr[NP], Ds[NP], DrT[NP], DsT[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
-    Dr[q] = Dg[i * NP + q];
-    Ds[q] = Dg[j * NP + q];
-    DrT[q] = Dg[q * NP + i];
-    DsT[q] = Dg[q * NP + j];
+    Dr[q] = Dgl[i * NP + q];
+    Ds[q] = Dgl[j * NP + q];
+    DrT[q] = Dgl[q * NP + i];
+    DsT[q] = Dgl[q * NP + j];
   }
 
-  T uk[NP];
+  // issue every load of the column up front: u (NP values) and the six
+  // geometric factors (6 NP values), so a wave has its whole element in flight
+  T uk[NP], gk[6][NP];
   if (active) {
-    const T* up = a.u + e * NP3 + ij;
+    const SEM_GLOBAL T* up = gl(a.u) + e * NP3 + ij;
+    const SEM_GLOBAL T* gp = gl(a.G) + e * 6 * NP3 + ij;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      uk[k] = up[k * NP2];
-      s_u[elc][k][j][i] = uk[k];
-    }
+    for (int k = 0; k < NP; ++k) uk[k] = __builtin_nontemporal_load(up + k * NP2);
+    // k-major issue order: the factors of slice k arrive before those of k+1
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+      for (int m = 0; m < 6; ++m) gk[m][k] = __builtin_nontemporal_load(gp + m * NP3 + k * NP2);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) s_u[elc][k][j][i] = uk[k];
   }
-  __syncthreads();
+  lds_sync<C::THREADS>();
 
   T wt[NP];
   if (active) {
-    const T* g = a.G + e * 6 * NP3 + ij;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
       T ur = 0, us = 0, ut = 0;
@@ -141,21 +180,26 @@ __global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, 
       for (int q = 0; q < NP; ++q) {
         ur += Dr[q] * s_u[elc][k][j][q];
         us += Ds[q] * s_u[elc][k][q][i];
-        ut += Dg[k * NP + q] * uk[q];
+        ut += Dgl[k * NP + q] * uk[q];
       }
-      const T grr = g[k * NP2], grs = g[NP3 + k * NP2], grt = g[2 * NP3 + k * NP2];
-      const T gss = g[3 * NP3 + k * NP2], gst = g[4 * NP3 + k * NP2], gtt = g[5 * NP3 + k * NP2];
+      const T grr = gk[0][k], grs = gk[1][k], grt = gk[2][k];
+      const T gss = gk[3][k], gst = gk[4][k], gtt = gk[5][k];
       s_wr[elc][k][j][i] = grr * ur + grs * us + grt * ut;
       s_ws[elc][k][j][i] = grs * ur + gss * us + gst * ut;
       wt[k] = grt * ur + gst * us + gtt * ut;
     }
   }
-  __syncthreads();
+  lds_sync<C::THREADS>();
 
   double dsum = 0.0;
   if (active) {
-    T* out = a.Au + e * NP3 + ij;
-    const T* Bp = a.B ? a.B + e * NP3 + ij : nullptr;
+    SEM_GLOBAL T* out = gl(a.Au) + e * NP3 + ij;
+    T bk[NP];
+    if constexpr (HELM) {
+      const SEM_GLOBAL T* Bp = gl(a.B) + e * NP3 + ij;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) bk[k] = (T)a.lambda * Bp[k * NP2];
+    }
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
       T au = 0;
@@ -163,16 +207,16 @@ __global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, 
       for (int q = 0; q < NP; ++q) {
         au += DrT[q] * s_wr[elc][k][j][q];
         au += DsT[q] * s_ws[elc][k][q][i];
-        au += Dg[q * NP + k] * wt[q];
+        au += Dgl[q * NP + k] * wt[q];
       }
-      if (Bp) au += (T)a.lambda * Bp[k * NP2] * uk[k];
-      out[k * NP2] = au;
+      if constexpr (HELM) au += bk[k] * uk[k];
+      __builtin_nontemporal_store(au, out + k * NP2);
       dsum += (double)uk[k] * (double)au;
     }
   }
   if (a.partial) {
     double s = block_sum<C::THREADS>(dsum, s_red);
-    if (tid == 0) a.partial[lb] = s;
+    if (tid == 0) gl(a.partial)[lb] = s;
   }
 }
 
@@ -192,10 +236,14 @@ int ax_blocks(int N, int64_t ne) {
 template <typename T>
 void launch_ax(int N, const Table<AxArgs<T>>& t, int64_t total_blocks, const T* D, hipStream_t s) {
   if (total_blocks <= 0) return;
+  const bool helm = t.many == nullptr && t.one.B != nullptr;
   switch (N) {
 #define SEM_AX_CASE(n)                                                                        \
   case n:                                                                                     \
-    hipLaunchKernelGGL((k_ax<n, T>), dim3((unsigned)total_blocks), dim3(AxCfg<n>::THREADS), 0, s, t, D); \
+    if (helm)                                                                                 \
+      hipLaunchKernelGGL((k_ax<n, T, true>), dim3((unsigned)total_blocks), dim3(AxCfg<n>::THREADS), 0, s, t, D); \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_ax<n, T, false>), dim3((unsigned)total_blocks), dim3(AxCfg<n>::THREADS), 0, s, t, D); \
     break;
     SEM_AX_CASE(1) SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5)
     SEM_AX_CASE(6) SEM_AX_CASE(7) SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10)
