@@ -74,7 +74,7 @@ def time_ax(sem, m, E, Np, steps, warmup):
     return wall, ms
 
 
-def solve_pair(sem, bm, m, label):
+def solve_pair(sem, bm, m, label, skip_pcg=False):
     import torch
     from paper_2110_01716_amd import workloads as wl
     out = {}
@@ -91,6 +91,9 @@ def solve_pair(sem, bm, m, label):
     out["pmg_fp32"] = {"seconds": time.perf_counter() - t, "iters": info["iters"], "relres": info["relres"],
                        "relres_true": info["relres_true"], "coarse_iters": info["coarse_iters"]}
     log(label, "pmg", out["pmg_fp32"])
+    if skip_pcg:
+        p.close()
+        return out
     xp = x.clone()
     t = time.perf_counter()
     info = sem.sem_pcg_solve(m.h, None, b, x, sem.solve_opts(rtol=1e-8, maxit=20000))
@@ -133,6 +136,8 @@ def main():
     ap.add_argument("--solve-c2", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--skip-pcg", action="store_true", help="time only the pMG solve")
+    ap.add_argument("--solve-only", action="store_true", help="skip the Ax steps (profiling the solve)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration under a profiler)")
     a = ap.parse_args()
@@ -154,6 +159,11 @@ def main():
         del src, dst
     spec = dict(wl.config_meshes()["ax_64x64x64_N7"])
     spec["n"] = a.n
+    if a.solve_only:
+        spec3 = wl.config_meshes()["pmg_48x48x48_N7"]
+        bm3, m3 = build_mesh(sem, spec3)
+        print(json.dumps({"poisson": {"48x48x48_N7": solve_pair(sem, bm3, m3, "c3", a.skip_pcg)}}), flush=True)
+        return
     bm, m = build_mesh(sem, spec)
     E, N = bm.E, bm.N
     Np = (N + 1) ** 3
@@ -193,7 +203,7 @@ def main():
         del bm
         spec3 = wl.config_meshes()["pmg_48x48x48_N7"]
         bm3, m3 = build_mesh(sem, spec3)
-        poisson["48x48x48_N7"] = solve_pair(sem, bm3, m3, "c3")
+        poisson["48x48x48_N7"] = solve_pair(sem, bm3, m3, "c3", a.skip_pcg)
         m3.close()
         res["poisson"] = poisson
     if not a.no_cpu:

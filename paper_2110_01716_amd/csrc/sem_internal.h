@@ -257,7 +257,7 @@ int ax_blocks(int N, int64_t ne);
 int64_t vec_blocks(int64_t n);
 int64_t gs_blocks(int64_t n_shared, int64_t n_dir);
 int xfer_blocks(int Nf, int Nc, int64_t E);
-constexpr int kFinThreads = 256;
+constexpr int kFinThreads = 1024;
 
 template <typename T>
 void launch_ax(int N, const Table<AxArgs<T>>& t, int64_t total_blocks, const T* D, hipStream_t s);

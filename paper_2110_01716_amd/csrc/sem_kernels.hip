@@ -260,26 +260,42 @@ template void launch_ax<float>(int, const Table<AxArgs<float>>&, int64_t, const 
 // ---------------------------------------------------------------------------
 // gather-scatter
 // ---------------------------------------------------------------------------
-constexpr int kGsThreads = 256;
+constexpr int kGsThreads = 128;
 
 template <typename T>
 __global__ __launch_bounds__(kGsThreads) void k_gs(Table<GsArgs<T>> tab) {
   int lb;
   const GsArgs<T> a = fetch_args(tab, blockIdx.x, lb);
   if (skipped(a.skip)) return;
+  SEM_GLOBAL T* v = gl(a.v);
+  const SEM_GLOBAL int* idx = gl(a.idx);
   const int64_t t = (int64_t)lb * kGsThreads + threadIdx.x;
   if (t < a.n_shared) {
-    const int q0 = a.off[t], q1 = a.off[t + 1];
-    if (a.mask && a.sdir[t]) {
-      for (int q = q0; q < q1; ++q) a.v[a.idx[q]] = T(0);
+    const int q0 = gl(a.off)[t], q1 = gl(a.off)[t + 1];
+    const int c = q1 - q0;
+    if (a.mask && gl(a.sdir)[t]) {
+      for (int q = q0; q < q1; ++q) v[idx[q]] = T(0);
+    } else if (c <= 8) {
+      // conforming hex meshes: at most 8 copies; issue all loads together
+      int id[8];
+      T val[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) id[q] = q < c ? idx[q0 + q] : 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) val[q] = q < c ? v[id[q]] : T(0);
+      T sum = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) if (q < c) sum += val[q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) if (q < c) v[id[q]] = sum;
     } else {
       T sum = 0;
-      for (int q = q0; q < q1; ++q) sum += a.v[a.idx[q]];
-      for (int q = q0; q < q1; ++q) a.v[a.idx[q]] = sum;
+      for (int q = q0; q < q1; ++q) sum += v[idx[q]];
+      for (int q = q0; q < q1; ++q) v[idx[q]] = sum;
     }
   } else if (a.mask) {
     const int64_t d = t - a.n_shared;
-    if (d < a.n_dir) a.v[a.dir_idx[d]] = T(0);
+    if (d < a.n_dir) v[gl(a.dir_idx)[d]] = T(0);
   }
 }
 
@@ -301,9 +317,17 @@ template void launch_gs<float>(const Table<GsArgs<float>>&, int64_t, hipStream_t
 // ---------------------------------------------------------------------------
 constexpr int kVecThreads = 256;
 constexpr int kVecPer = 8;
-constexpr int kVecChunk = kVecThreads * kVecPer;
 
-int64_t vec_blocks(int64_t n) { return (n + kVecChunk - 1) / kVecChunk; }
+// points per thread: few for small vectors (enough blocks to fill 256 CUs),
+// more for large ones (fewer partial sums to reduce)
+__host__ __device__ __forceinline__ int vec_per(int64_t n) {
+  return n >= (int64_t(1) << 24) ? 8 : n >= (int64_t(1) << 21) ? 4 : n >= (int64_t(1) << 19) ? 2 : 1;
+}
+
+int64_t vec_blocks(int64_t n) {
+  const int64_t chunk = (int64_t)kVecThreads * vec_per(n);
+  return (n + chunk - 1) / chunk;
+}
 
 template <typename T, int OP>
 __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
@@ -311,80 +335,91 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
   int lb;
   const VecArgs<T> a = fetch_args(tab, blockIdx.x, lb);
   if (skipped(a.skip)) return;
-  const int64_t base = (int64_t)lb * kVecChunk + threadIdx.x;
+  SEM_GLOBAL T* X = gl(a.x);
+  SEM_GLOBAL T* R = gl(a.r);
+  SEM_GLOBAL T* P = gl(a.p);
+  SEM_GLOBAL T* W = gl(a.w);
+  SEM_GLOBAL T* Z = gl(a.z);
+  SEM_GLOBAL T* Tt = gl(a.t);
+  SEM_GLOBAL T* RES = gl(a.res);
+  SEM_GLOBAL T* Dd = gl(a.d);
+  const SEM_GLOBAL T* DINV = gl(a.dinv);
+  const SEM_GLOBAL uint8_t* OWN = gl(a.owner);
+  const int per = vec_per(a.n);
+  const int64_t base = (int64_t)lb * kVecThreads * per + threadIdx.x;
   double acc0 = 0.0, acc1 = 0.0;
   T alpha = 0, beta = 0, scale = 0;
-  if constexpr (OP == V_PCG_UPDATE) alpha = (T)a.scal[S_ALPHA];
-  if constexpr (OP == V_P_JACOBI || OP == V_P_FLEX) beta = (T)a.scal[S_BETA];
-  if constexpr (OP == V_NORMALIZE) scale = (T)a.scal[S_TMP];
+  if constexpr (OP == V_PCG_UPDATE) alpha = (T)gl(a.scal)[S_ALPHA];
+  if constexpr (OP == V_P_JACOBI || OP == V_P_FLEX) beta = (T)gl(a.scal)[S_BETA];
+  if constexpr (OP == V_NORMALIZE) scale = (T)gl(a.scal)[S_TMP];
   const T c0 = (T)a.c0, c1 = (T)a.c1, c2 = (T)a.c2;
 #pragma unroll
   for (int q = 0; q < kVecPer; ++q) {
     const int64_t l = base + (int64_t)q * kVecThreads;
-    if (l >= a.n) break;
+    if (q >= per || l >= a.n) break;
     if constexpr (OP == V_PCG_UPDATE) {
-      a.x[l] += alpha * a.p[l];
-      const T rn = a.r[l] - alpha * a.w[l];
-      a.r[l] = rn;
-      if (a.owner[l]) {
+      X[l] += alpha * P[l];
+      const T rn = R[l] - alpha * W[l];
+      R[l] = rn;
+      if (OWN[l]) {
         acc0 += (double)rn * (double)rn;
-        if (a.dinv) acc1 += (double)rn * (double)a.dinv[l] * (double)rn;
+        if (DINV) acc1 += (double)rn * (double)DINV[l] * (double)rn;
       }
     } else if constexpr (OP == V_P_JACOBI) {
-      a.p[l] = a.dinv[l] * a.r[l] + beta * a.p[l];
+      P[l] = DINV[l] * R[l] + beta * P[l];
     } else if constexpr (OP == V_P_FLEX) {
-      a.p[l] = a.z[l] + beta * a.p[l];
+      P[l] = Z[l] + beta * P[l];
     } else if constexpr (OP == V_DOT2) {
-      if (a.owner[l]) {
-        const double zl = (double)a.z[l];
-        acc0 += zl * (double)a.w[l];
-        acc1 += zl * (double)a.r[l];
+      if (OWN[l]) {
+        const double zl = (double)Z[l];
+        acc0 += zl * (double)W[l];
+        acc1 += zl * (double)R[l];
       }
     } else if constexpr (OP == V_DOT1) {
-      if (a.owner[l]) acc0 += (double)a.r[l] * (double)a.r[l];
+      if (OWN[l]) acc0 += (double)R[l] * (double)R[l];
     } else if constexpr (OP == V_RZ_JACOBI) {
-      const T pz = a.dinv[l] * a.r[l];
-      a.p[l] = pz;
-      if (a.owner[l]) acc0 += (double)a.r[l] * (double)pz;
+      const T pz = DINV[l] * R[l];
+      P[l] = pz;
+      if (OWN[l]) acc0 += (double)R[l] * (double)pz;
     } else if constexpr (OP == V_CHEB_INIT0) {
-      const T d = c0 * a.dinv[l] * a.r[l];
-      a.d[l] = d;
-      a.x[l] = d;
+      const T d = c0 * DINV[l] * R[l];
+      Dd[l] = d;
+      X[l] = d;
     } else if constexpr (OP == V_CHEB_INITX) {
-      const T res = a.r[l] - a.t[l];
-      a.res[l] = res;
-      const T d = c0 * a.dinv[l] * res;
-      a.d[l] = d;
-      a.x[l] += d;
+      const T res = R[l] - Tt[l];
+      RES[l] = res;
+      const T d = c0 * DINV[l] * res;
+      Dd[l] = d;
+      X[l] += d;
     } else if constexpr (OP == V_CHEB_STEP0) {
-      const T res = a.r[l] - a.t[l];
-      a.res[l] = res;
-      const T d = c1 * a.d[l] + c2 * a.dinv[l] * res;
-      a.d[l] = d;
-      a.x[l] += d;
+      const T res = R[l] - Tt[l];
+      RES[l] = res;
+      const T d = c1 * Dd[l] + c2 * DINV[l] * res;
+      Dd[l] = d;
+      X[l] += d;
     } else if constexpr (OP == V_CHEB_STEP) {
-      const T res = a.res[l] - a.t[l];
-      a.res[l] = res;
-      const T d = c1 * a.d[l] + c2 * a.dinv[l] * res;
-      a.d[l] = d;
-      a.x[l] += d;
+      const T res = RES[l] - Tt[l];
+      RES[l] = res;
+      const T d = c1 * Dd[l] + c2 * DINV[l] * res;
+      Dd[l] = d;
+      X[l] += d;
     } else if constexpr (OP == V_ZERO) {
-      a.x[l] = T(0);
+      X[l] = T(0);
     } else if constexpr (OP == V_COPY) {
-      a.x[l] = a.r[l];
+      X[l] = R[l];
     } else if constexpr (OP == V_SCALE_DINV) {
-      a.x[l] = a.dinv[l] * a.r[l];
+      X[l] = DINV[l] * R[l];
     } else if constexpr (OP == V_NORMALIZE) {
-      a.x[l] = a.r[l] * scale;
+      X[l] = R[l] * scale;
     } else if constexpr (OP == V_TRUE_RES) {
-      if (a.owner[l]) {
-        const double e = (double)a.r[l] - (double)a.t[l];
+      if (OWN[l]) {
+        const double e = (double)R[l] - (double)Tt[l];
         acc0 += e * e;
       }
     } else if constexpr (OP == V_DIV_DINV) {
-      a.x[l] = a.dinv[l] != T(0) ? a.r[l] / a.dinv[l] : T(0);
+      X[l] = DINV[l] != T(0) ? R[l] / DINV[l] : T(0);
     } else if constexpr (OP == V_SCALE) {
-      a.x[l] = c0 * a.r[l];
+      X[l] = c0 * R[l];
     }
   }
   constexpr bool RED = (OP == V_PCG_UPDATE || OP == V_DOT2 || OP == V_DOT1 || OP == V_RZ_JACOBI ||
@@ -397,8 +432,8 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
     if (threadIdx.x == 0) {
       double t0 = 0.0, t1 = 0.0;
       for (int k = 0; k < kVecThreads / 64; ++k) { t0 += s_red[0][k]; t1 += s_red[1][k]; }
-      a.partial[lb] = t0;
-      a.partial[a.stride + lb] = t1;
+      gl(a.partial)[lb] = t0;
+      gl(a.partial)[a.stride + lb] = t1;
     }
   }
 }
@@ -429,11 +464,12 @@ __global__ __launch_bounds__(kVecThreads) void k_cast(Table<CastArgs<Tin, Tout>>
   int lb;
   const CastArgs<Tin, Tout> a = fetch_args(tab, blockIdx.x, lb);
   if (skipped(a.skip)) return;
-  const int64_t base = (int64_t)lb * kVecChunk + threadIdx.x;
+  const int per = vec_per(a.n);
+  const int64_t base = (int64_t)lb * kVecThreads * per + threadIdx.x;
 #pragma unroll
   for (int q = 0; q < kVecPer; ++q) {
     const int64_t l = base + (int64_t)q * kVecThreads;
-    if (l < a.n) a.out[l] = (Tout)a.in[l];
+    if (q < per && l < a.n) gl(a.out)[l] = (Tout)gl(a.in)[l];
   }
 }
 
@@ -452,29 +488,53 @@ template void launch_cast<float, float>(const Table<CastArgs<float, float>>&, in
 // finalize: per-problem fixed-order reduction + scalar recurrences
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kFinThreads) void k_fin(Table<FinArgs> tab, int op) {
-  __shared__ double s_red[2][kFinThreads];
-  const FinArgs a = tab.many ? tab.many[blockIdx.x] : tab.one;
+  __shared__ double s_red[2][kFinThreads / 64];
+  FinArgs a = tab.one;
+  if (tab.many) a = gl(tab.many)[blockIdx.x];
   if (skipped(a.skip)) return;
   double s0 = 0.0, s1 = 0.0;
-  for (int64_t k = threadIdx.x; k < a.nblk; k += kFinThreads) {
-    s0 += a.partial[k];
-    s1 += a.partial[a.stride + k];
+  const SEM_GLOBAL double* part = gl(a.partial);
+  // thread t sums partials t, t+T, t+2T, ... into 4 interleaved accumulators
+  // (independent loads in flight), then a fixed butterfly + wave-order sum
+  constexpr int T4 = 4 * kFinThreads;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+  int64_t k = threadIdx.x;
+  for (; k + 3 * kFinThreads < a.nblk; k += T4) {
+    a0 += part[k];
+    a1 += part[k + kFinThreads];
+    a2 += part[k + 2 * kFinThreads];
+    a3 += part[k + 3 * kFinThreads];
+    b0 += part[a.stride + k];
+    b1 += part[a.stride + k + kFinThreads];
+    b2 += part[a.stride + k + 2 * kFinThreads];
+    b3 += part[a.stride + k + 3 * kFinThreads];
   }
-  s_red[0][threadIdx.x] = s0;
-  s_red[1][threadIdx.x] = s1;
+  for (; k < a.nblk; k += kFinThreads) {
+    a0 += part[k];
+    b0 += part[a.stride + k];
+  }
+  s0 = wave_sum((a0 + a1) + (a2 + a3));
+  s1 = wave_sum((b0 + b1) + (b2 + b3));
+  if ((threadIdx.x & 63) == 0) {
+    s_red[0][threadIdx.x >> 6] = s0;
+    s_red[1][threadIdx.x >> 6] = s1;
+  }
   __syncthreads();
-  for (int w = kFinThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      s_red[0][threadIdx.x] += s_red[0][threadIdx.x + w];
-      s_red[1][threadIdx.x] += s_red[1][threadIdx.x + w];
+  if (threadIdx.x == 0) {
+    s0 = 0.0;
+    s1 = 0.0;
+    for (int w = 0; w < kFinThreads / 64; ++w) {
+      s0 += s_red[0][w];
+      s1 += s_red[1][w];
     }
-    __syncthreads();
+    s_red[0][0] = s0;
+    s_red[1][0] = s1;
   }
   if (threadIdx.x != 0) return;
   s0 = s_red[0][0];
   s1 = s_red[1][0];
-  double* sc = a.scal;
-  int* fl = a.flags;
+  SEM_GLOBAL double* sc = gl(a.scal);
+  SEM_GLOBAL int* fl = gl(a.flags);
   switch (op) {
     case FIN_INIT:
       sc[S_BB] = s0;
@@ -505,7 +565,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin(Table<FinArgs> tab, int op)
     case FIN_CHECK_JACOBI: {
       sc[S_RR] = s0;
       const int it = ++fl[F_ITERS];
-      if (a.total) ++(*a.total);
+      if (a.total) ++(*gl(a.total));
       const double rel = sqrt(s0 / sc[S_BB]);
       sc[S_RELRES] = rel;
       if (!isfinite(s0)) { fl[F_STATUS] = SEM_ENAN; fl[F_DONE] = 1; }
@@ -615,11 +675,11 @@ __global__ __launch_bounds__(kXferThreads) void k_xfer(Table<XferArgs<Tf, Tc>> t
     if (e < a.E) {
       const int64_t g = e * C::S0 + r;
       if constexpr (DIR == 0) {
-        v = (Tf)a.zc[g];
+        v = (Tf)gl(a.zc)[g];
       } else {
-        v = a.rf[g];
-        if (a.tf) v -= a.tf[g];
-        if (!a.owner_f[g]) v = 0;
+        v = gl(a.rf)[g];
+        if (a.tf) v -= gl(a.tf)[g];
+        if (!gl(a.owner_f)[g]) v = 0;
       }
     }
     s0[el][r] = v;
@@ -631,8 +691,8 @@ __global__ __launch_bounds__(kXferThreads) void k_xfer(Table<XferArgs<Tf, Tc>> t
     const int64_t e = e_first + el;
     if (e >= a.E) continue;
     const int64_t g = e * C::S3 + r;
-    if constexpr (DIR == 0) a.xf[g] += s3[el][r];
-    else a.out_c[g] = (Tc)s3[el][r];
+    if constexpr (DIR == 0) gl(a.xf)[g] += s3[el][r];
+    else gl(a.out_c)[g] = (Tc)s3[el][r];
   }
 }
 
