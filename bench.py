@@ -107,6 +107,92 @@ def solve_pair(sem, bm, m, label, skip_pcg=False):
     return out
 
 
+def bench_batched(sem, count=256, sequential=True):
+    """Independent Dirichlet problems (m^3 elements, m ~ U{2..12}; N ~ U{5,7,9};
+    deformed boxes; seeded RHS) solved by FP64 flexible CG + FP32 pMG: one
+    batched call (each phase one launch over all problems) vs one call each."""
+    import torch
+    from paper_2110_01716_amd import workloads as wl
+    t = time.time()
+    specs = wl.batched_problem_specs(count)
+    meshes, pmgs, bs = [], [], []
+    for k, sp in enumerate(specs):
+        bm = wl.box_mesh(sp["n"], N=sp["N"], deform=sp["deform"], seed=sp["seed"])
+        m = sem.Mesh.from_box(bm)
+        meshes.append(m)
+        pmgs.append(sem.Pmg(m))
+        bs.append(torch.from_numpy(wl.random_rhs(bm, 2000 + k)).to("cuda"))
+    setup = time.time() - t
+    npts = sum(m.E * m.Np for m in meshes)
+    xb = [torch.empty_like(b) for b in bs]
+    opts = sem.solve_opts(rtol=1e-8)
+    sem.sem_pcg_solve_batched([m.h for m in meshes], [p.h for p in pmgs], bs, xb, opts)  # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rc, infos = sem.sem_pcg_solve_batched([m.h for m in meshes], [p.h for p in pmgs], bs, xb, opts)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    out = {"problems": count, "local_points": npts, "setup_s": round(setup, 2), "batched_s": round(tb, 4),
+           "batched_solves_per_s": round(count / tb, 1), "status_ok": all(i["status"] == 0 for i in infos),
+           "max_relres_true": max(i["relres_true"] for i in infos),
+           "iters_mean": float(np.mean([i["iters"] for i in infos])), "iters_max": max(i["iters"] for i in infos)}
+    if sequential:
+        xs = [torch.empty_like(b) for b in bs]
+        t = time.perf_counter()
+        for m, p, b, x in zip(meshes, pmgs, bs, xs):
+            sem.sem_pcg_solve(m.h, p.h, b, x, opts)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t
+        out["sequential_s"] = round(ts, 4)
+        out["speedup_batched_vs_sequential"] = round(ts / tb, 2)
+        out["bitwise_equal_to_alone"] = all(torch.equal(a, b) for a, b in zip(xs, xb))
+    for p in pmgs:
+        p.close()
+    for m in meshes:
+        m.close()
+    return out
+
+
+def bench_serving(sem, rates=(10, 20, 50, 100, 200, 500), window_s=2.0, max_slots=32):
+    """Poisson arrivals on 16 resident N=7 deformed-box meshes of m^3 elements,
+    m = round(8 + 32 i / 15); each request solves to 1e-8 (FP64 flexible CG,
+    FP32 pMG); admission by HBM footprint; p50/p99 arrival-to-result latency."""
+    import torch
+    from paper_2110_01716_amd import serving, workloads as wl
+    t = time.time()
+    sides = wl.serving_mesh_sides()
+    resident, pool = [], {}
+    for k, n in enumerate(sides):
+        bm = wl.box_mesh(n, N=7, deform=0.05, seed=1000 + k)
+        m = sem.Mesh.from_box(bm)
+        resident.append((m, sem.Pmg(m)))
+        for j in range(2):
+            pool[(k, j)] = torch.from_numpy(wl.random_rhs(bm, 2000 + 2 * k + j)).to("cuda")
+        del bm
+    setup = time.time() - t
+    srv = serving.Server(resident, max_slots=max_slots)
+    warm = [serving.Request(rid=k, mesh=k, rhs=pool[(k, 0)], arrival=0.0) for k in range(len(sides))]
+    srv.run(warm, realtime=False)
+    out = {"meshes": sides, "setup_s": round(setup, 1), "max_slots": max_slots,
+           "hbm_budget_GB": round(srv.hbm_budget / 1e9, 1), "rates": {}}
+    for rate in rates:
+        n = int(min(max(rate * window_s, 24), 240))
+        arr = serving.poisson_arrivals(n, rate, len(sides), seed=5000 + rate)
+        reqs = [serving.Request(rid=i, mesh=k, rhs=pool[(k, i % 2)], arrival=tt) for i, (tt, k) in enumerate(arr)]
+        st = srv.run(reqs, realtime=True)
+        s = st.summary()
+        s["offered_rate"] = rate
+        s["requests"] = n
+        s["all_ok"] = all(r.info["status"] == 0 for r in reqs)
+        out["rates"][str(rate)] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in s.items()}
+        log("serving", rate, out["rates"][str(rate)])
+    srv.close()
+    for m, p in resident:
+        p.close()
+        m.close()
+    return out
+
+
 def cpu_baseline(bm_spec, budget_s=12.0):
     """Oracle Ax (FP64 NumPy) on a bounded sample of the workload, 1 thread."""
     from threadpoolctl import threadpool_limits
@@ -137,6 +223,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--skip-pcg", action="store_true", help="time only the pMG solve")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--batched-only", action="store_true")
+    ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--solve-only", action="store_true", help="skip the Ax steps (profiling the solve)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration under a profiler)")
@@ -159,6 +249,12 @@ def main():
         del src, dst
     spec = dict(wl.config_meshes()["ax_64x64x64_N7"])
     spec["n"] = a.n
+    if a.batched_only:
+        print(json.dumps({"batched": bench_batched(sem)}), flush=True)
+        return
+    if a.serving_only:
+        print(json.dumps({"serving": bench_serving(sem)}), flush=True)
+        return
     if a.solve_only:
         spec3 = wl.config_meshes()["pmg_48x48x48_N7"]
         bm3, m3 = build_mesh(sem, spec3)
@@ -206,6 +302,11 @@ def main():
         poisson["48x48x48_N7"] = solve_pair(sem, bm3, m3, "c3", a.skip_pcg)
         m3.close()
         res["poisson"] = poisson
+    if not a.no_batched:
+        res["batched"] = bench_batched(sem)
+        log("batched", res["batched"])
+    if not a.no_serving:
+        res["serving"] = bench_serving(sem)
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(res), flush=True)
