@@ -95,6 +95,7 @@ struct Slot {
   void *lr[kMaxLevels] = {}, *lx[kMaxLevels] = {}, *lres[kMaxLevels] = {}, *ld[kMaxLevels] = {},
        *lt[kMaxLevels] = {};
   double *cr = nullptr, *cx = nullptr, *cp = nullptr, *cw = nullptr;
+  double* clocal = nullptr;  // restriction output on coarse element storage (assembled coarse level)
   double* partial = nullptr;
   int64_t stride = 0;
   int idx = -1;
@@ -140,11 +141,17 @@ size_t layout(Slot& s, uint8_t* base) {
       s.lt[l] = take(ts * nl);
     }
     const MeshData& c = s.level(L - 1);
-    s.cr = (double*)take(8 * c.nloc);
-    s.cx = (double*)take(8 * c.nloc);
-    s.cp = (double*)take(8 * c.nloc);
-    s.cw = (double*)take(8 * c.nloc);
-    stride = std::max<int64_t>(stride, std::max<int64_t>(ax_blocks(c.N, c.E), vec_blocks(c.nloc)));
+    const int64_t nc = c.assembled ? c.n_unique : c.nloc;
+    s.cr = (double*)take(8 * nc);
+    s.cx = (double*)take(8 * nc);
+    s.cp = (double*)take(8 * nc);
+    s.cw = (double*)take(8 * nc);
+    if (c.assembled) {
+      s.clocal = (double*)take(8 * c.nloc);
+      stride = std::max<int64_t>(stride, std::max<int64_t>(spmv_blocks(nc), vec_blocks(nc)));
+    } else {
+      stride = std::max<int64_t>(stride, std::max<int64_t>(ax_blocks(c.N, c.E), vec_blocks(c.nloc)));
+    }
   }
   s.stride = stride;
   s.partial = (double*)take(8 * 2 * stride);
@@ -277,24 +284,72 @@ class Plan {
     add(seq, args, starts, [total](const Table<GsArgs<T>>& t, hipStream_t st) { launch_gs<T>(t, total, st); });
   }
 
+  // uniq: the vectors live on the unique DOFs of an assembled level
   template <typename T, typename F>
-  void vec(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, VecOp op, F fill, int skip_mode) {
+  void vec(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, VecOp op, F fill, int skip_mode,
+           bool uniq = false) {
     std::vector<VecArgs<T>> args;
     std::vector<int> starts{0};
     for (Slot* s : S) {
       const MeshData& m = s->level(l);
       VecArgs<T> a;
-      a.n = m.nloc;
-      a.owner = m.owner.as<uint8_t>();
+      a.n = uniq ? m.n_unique : m.nloc;
+      a.owner = uniq ? nullptr : m.owner.as<uint8_t>();
       a.partial = s->partial;
       a.stride = s->stride;
       a.skip = skip(*s, skip_mode);
       fill(*s, a);
       args.push_back(a);
-      starts.push_back(starts.back() + (int)vec_blocks(m.nloc));
+      starts.push_back(starts.back() + (int)vec_blocks(a.n));
     }
     const int64_t total = starts.back();
     add(seq, args, starts, [op, total](const Table<VecArgs<T>>& t, hipStream_t st) { launch_vec<T>(op, t, total, st); });
+  }
+
+  // y = A x on the unique DOFs of assembled level l (optionally the partials of x . y)
+  template <typename FX, typename FY>
+  void spmv(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, FX x_of, FY y_of, bool with_partial,
+            int skip_mode) {
+    std::vector<SpmvArgs> args;
+    std::vector<int> starts{0};
+    for (Slot* s : S) {
+      const MeshData& m = s->level(l);
+      SpmvArgs a;
+      a.n = m.n_unique;
+      a.W = m.ell_w;
+      a.col = m.ell_col.as<int>();
+      a.val = m.ell_val.as<double>();
+      a.x = x_of(*s);
+      a.y = y_of(*s);
+      a.partial = with_partial ? s->partial : nullptr;
+      a.skip = skip(*s, skip_mode);
+      args.push_back(a);
+      starts.push_back(starts.back() + (int)spmv_blocks(a.n));
+    }
+    const int64_t total = starts.back();
+    add(seq, args, starts, [total](const Table<SpmvArgs>& t, hipStream_t st) { launch_spmv(t, total, st); });
+  }
+
+  // out (unique DOFs) = masked sum of the element-storage copies in `in`
+  template <typename FI, typename FO>
+  void usum(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, FI in_of, FO out_of, int skip_mode) {
+    std::vector<UsumArgs> args;
+    std::vector<int> starts{0};
+    for (Slot* s : S) {
+      const MeshData& m = s->level(l);
+      UsumArgs a;
+      a.n = m.n_unique;
+      a.off = m.u2l_off.as<int>();
+      a.idx = m.u2l_idx.as<int>();
+      a.udir = m.udir.as<uint8_t>();
+      a.in = in_of(*s);
+      a.out = out_of(*s);
+      a.skip = skip(*s, skip_mode);
+      args.push_back(a);
+      starts.push_back(starts.back() + (int)spmv_blocks(a.n));
+    }
+    const int64_t total = starts.back();
+    add(seq, args, starts, [total](const Table<UsumArgs>& t, hipStream_t st) { launch_usum(t, total, st); });
   }
 
   template <typename Tin, typename Tout, typename F>
@@ -457,13 +512,17 @@ void Plan::build_vcycle(Group& g) {
     }
     const bool pre = o.pre > 0;
     if (l + 2 == L) {
-      xfer<T, double>(seq, S, l, 1, [l, Tp, pre](Slot& s, XferArgs<T, double>& a) {
+      const bool asmb = S[0]->level(L - 1).assembled;
+      xfer<T, double>(seq, S, l, 1, [l, Tp, pre, asmb](Slot& s, XferArgs<T, double>& a) {
         a.rf = Tp(s.lr[l]);
         a.tf = pre ? Tp(s.lt[l]) : nullptr;
         a.owner_f = s.level(l).owner.as<uint8_t>();
-        a.out_c = s.cr;
+        a.out_c = asmb ? s.clocal : s.cr;
       }, SK);
-      gs<double>(seq, S, l + 1, [](Slot& s) { return s.cr; }, SK);
+      if (asmb)
+        usum(seq, S, l + 1, [](Slot& s) { return (const double*)s.clocal; }, [](Slot& s) { return s.cr; }, SK);
+      else
+        gs<double>(seq, S, l + 1, [](Slot& s) { return s.cr; }, SK);
     } else {
       xfer<T, T>(seq, S, l, 1, [l, Tp, pre](Slot& s, XferArgs<T, T>& a) {
         a.rf = Tp(s.lr[l]);
@@ -475,48 +534,57 @@ void Plan::build_vcycle(Group& g) {
     }
   }
 
-  // coarse Jacobi-PCG, FP64
+  // coarse Jacobi-PCG, FP64 (on unique DOFs when the level is assembled)
   {
     const int c = L - 1;
+    const bool U = S[0]->level(c).assembled;
     g.coarse_limit = o.coarse_fixed_iters > 0 ? o.coarse_fixed_iters : o.coarse_maxit;
     g.coarse_fixed = o.coarse_fixed_iters;
     g.coarse_check = o.coarse_check_every;
-    vec<double>(g.cinit, S, c, V_ZERO, [](Slot& s, VecArgs<double>& a) { a.x = s.cx; }, SK);
-    vec<double>(g.cinit, S, c, V_DOT1, [](Slot& s, VecArgs<double>& a) { a.r = s.cr; }, SK);
-    fin(g.cinit, S, FIN_INIT, 1, [c](Slot& s) { return vec_blocks(s.level(c).nloc); }, SK);
-    vec<double>(g.cinit, S, c, V_RZ_JACOBI, [c](Slot& s, VecArgs<double>& a) {
+    auto nvec = [c, U](Slot& s) { return vec_blocks(U ? s.level(c).n_unique : s.level(c).nloc); };
+    auto cdinv = [c, U](Slot& s) { return U ? s.level(c).dinv_u.as<double>() : s.level(c).dinv64.as<double>(); };
+    vec<double>(g.cinit, S, c, V_ZERO, [](Slot& s, VecArgs<double>& a) { a.x = s.cx; }, SK, U);
+    vec<double>(g.cinit, S, c, V_DOT1, [](Slot& s, VecArgs<double>& a) { a.r = s.cr; }, SK, U);
+    fin(g.cinit, S, FIN_INIT, 1, nvec, SK);
+    vec<double>(g.cinit, S, c, V_RZ_JACOBI, [cdinv](Slot& s, VecArgs<double>& a) {
       a.r = s.cr;
       a.p = s.cp;
-      a.dinv = s.level(c).dinv64.as<double>();
-    }, SK);
-    fin(g.cinit, S, FIN_RZ, 1, [c](Slot& s) { return vec_blocks(s.level(c).nloc); }, SK);
+      a.dinv = cdinv(s);
+    }, SK, U);
+    fin(g.cinit, S, FIN_RZ, 1, nvec, SK);
 
-    apply_A<double>(g.citer, S, c, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2);
-    fin(g.citer, S, FIN_ALPHA, 1, [c](Slot& s) { return (int64_t)ax_blocks(s.level(c).N, s.level(c).E); }, 2);
-    vec<double>(g.citer, S, c, V_PCG_UPDATE, [c](Slot& s, VecArgs<double>& a) {
+    if (U) {
+      spmv(g.citer, S, c, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2);
+      fin(g.citer, S, FIN_ALPHA, 1, [c](Slot& s) { return spmv_blocks(s.level(c).n_unique); }, 2);
+    } else {
+      apply_A<double>(g.citer, S, c, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2);
+      fin(g.citer, S, FIN_ALPHA, 1, [c](Slot& s) { return (int64_t)ax_blocks(s.level(c).N, s.level(c).E); }, 2);
+    }
+    vec<double>(g.citer, S, c, V_PCG_UPDATE, [cdinv](Slot& s, VecArgs<double>& a) {
       a.x = s.cx;
       a.p = s.cp;
       a.r = s.cr;
       a.w = s.cw;
-      a.dinv = s.level(c).dinv64.as<double>();
+      a.dinv = cdinv(s);
       a.scal = s.scal[1];
-    }, 2);
-    fin(g.citer, S, FIN_CHECK_JACOBI, 1, [c](Slot& s) { return vec_blocks(s.level(c).nloc); }, 2,
-        o.coarse_rtol, o.coarse_fixed_iters > 0 ? (1 << 30) : o.coarse_maxit, o.coarse_fixed_iters, true);
-    vec<double>(g.citer, S, c, V_P_JACOBI, [c](Slot& s, VecArgs<double>& a) {
+    }, 2, U);
+    fin(g.citer, S, FIN_CHECK_JACOBI, 1, nvec, 2, o.coarse_rtol,
+        o.coarse_fixed_iters > 0 ? (1 << 30) : o.coarse_maxit, o.coarse_fixed_iters, true);
+    vec<double>(g.citer, S, c, V_P_JACOBI, [cdinv](Slot& s, VecArgs<double>& a) {
       a.p = s.cp;
       a.r = s.cr;
-      a.dinv = s.level(c).dinv64.as<double>();
+      a.dinv = cdinv(s);
       a.scal = s.scal[1];
-    }, 2);
+    }, 2, U);
   }
 
   // up-sweep
   for (int l = L - 2; l >= 0; --l) {
     auto& seq = g.tail;
     if (l + 2 == L) {
-      xfer<T, double>(seq, S, l, 0, [l, Tp](Slot& s, XferArgs<T, double>& a) {
+      xfer<T, double>(seq, S, l, 0, [l, L, Tp](Slot& s, XferArgs<T, double>& a) {
         a.zc = s.cx;
+        a.umap_c = s.level(L - 1).assembled ? s.level(L - 1).umap.as<int>() : nullptr;
         a.xf = Tp(s.lx[l]);
       }, SK);
     } else {

@@ -102,6 +102,16 @@ struct MeshData {
   DevBuf gs_idx;           // int32 [n_shared_entries]
   DevBuf gs_dir;           // uint8 [n_shared]  1 = Dirichlet node
   DevBuf dir_idx;          // int32 [n_dir_single]  Dirichlet copies of unshared IDs
+  // assembled form on unique DOFs (coarsest pMG level only)
+  bool assembled = false;
+  int ell_w = 0;           // ELL width (longest row)
+  DevBuf umap;             // int32 [nloc]  unique index of each copy
+  DevBuf u2l_off;          // int32 [n_unique+1]  copies of each unique DOF (CSR)
+  DevBuf u2l_idx;          // int32 [nloc]  local indices, ascending within a DOF
+  DevBuf udir;             // uint8 [n_unique]  Dirichlet DOF
+  DevBuf dinv_u;           // f64 [n_unique]  inverse diagonal, 0 on Dirichlet
+  DevBuf ell_col;          // int32 [W][n_unique]
+  DevBuf ell_val;          // f64 [W][n_unique]
   int64_t resident_bytes() const;
 };
 
@@ -239,6 +249,7 @@ struct FinArgs {
 template <typename Tf, typename Tc>
 struct XferArgs {
   int64_t E = 0;
+  const int* umap_c = nullptr;  // prolong from a unique-DOF coarse vector: zc[umap_c[local]]
   // restrict: out_c = (J^T)^3 ((rf - tf) . owner_f)   (tf may be null)
   const Tf* rf = nullptr;
   const Tf* tf = nullptr;
@@ -247,6 +258,29 @@ struct XferArgs {
   // prolong: xf += J^3 zc
   const Tc* zc = nullptr;
   Tf* xf = nullptr;
+  Skip skip;
+};
+
+// y = A x on unique DOFs (ELL), partial per block: sum x . y
+struct SpmvArgs {
+  int64_t n = 0;
+  int W = 0;
+  const int* col = nullptr;
+  const double* val = nullptr;
+  const double* x = nullptr;
+  double* y = nullptr;
+  double* partial = nullptr;
+  Skip skip;
+};
+
+// out[r] = 0 on Dirichlet DOFs, else sum of the local copies of DOF r (Q^T)
+struct UsumArgs {
+  int64_t n = 0;
+  const int* off = nullptr;
+  const int* idx = nullptr;
+  const uint8_t* udir = nullptr;
+  const double* in = nullptr;
+  double* out = nullptr;
   Skip skip;
 };
 
@@ -268,6 +302,9 @@ void launch_vec(VecOp op, const Table<VecArgs<T>>& t, int64_t total_blocks, hipS
 template <typename Tin, typename Tout>
 void launch_cast(const Table<CastArgs<Tin, Tout>>& t, int64_t total_blocks, hipStream_t s);
 void launch_fin(FinOp op, const Table<FinArgs>& t, int nprob, hipStream_t s);
+int64_t spmv_blocks(int64_t n);
+void launch_spmv(const Table<SpmvArgs>& t, int64_t total_blocks, hipStream_t s);
+void launch_usum(const Table<UsumArgs>& t, int64_t total_blocks, hipStream_t s);
 template <typename Tf, typename Tc>
 void launch_xfer(int dir, int Nf, int Nc, const Table<XferArgs<Tf, Tc>>& t, int64_t total_blocks,
                  const double* J, hipStream_t s);
@@ -284,6 +321,8 @@ void launch_mass(int N, int64_t nloc, int is_f32, const void* B, const void* u, 
 
 // gather-scatter map construction (sem_gsmap.hip)
 void build_gs_map(MeshData& m, hipStream_t s);
+// assembled unique-DOF operator (sem_assemble.hip)
+void build_assembled(MeshData& m, hipStream_t s);
 
 // mesh construction from device coordinates and host IDs/flags (sem_mesh.cpp)
 void build_mesh(MeshData& m, int N, int64_t E, const int64_t* gid_host, const uint8_t* dir_host,

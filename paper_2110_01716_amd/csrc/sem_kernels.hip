@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
   SEM_GLOBAL T* RES = gl(a.res);
   SEM_GLOBAL T* Dd = gl(a.d);
   const SEM_GLOBAL T* DINV = gl(a.dinv);
-  const SEM_GLOBAL uint8_t* OWN = gl(a.owner);
+  const SEM_GLOBAL uint8_t* OWN = gl(a.owner);  // null: every entry counts (unique-DOF vectors)
   const int per = vec_per(a.n);
   const int64_t base = (int64_t)lb * kVecThreads * per + threadIdx.x;
   double acc0 = 0.0, acc1 = 0.0;
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
       X[l] += alpha * P[l];
       const T rn = R[l] - alpha * W[l];
       R[l] = rn;
-      if (OWN[l]) {
+      if (!OWN || OWN[l]) {
         acc0 += (double)rn * (double)rn;
         if (DINV) acc1 += (double)rn * (double)DINV[l] * (double)rn;
       }
@@ -370,17 +370,17 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
     } else if constexpr (OP == V_P_FLEX) {
       P[l] = Z[l] + beta * P[l];
     } else if constexpr (OP == V_DOT2) {
-      if (OWN[l]) {
+      if (!OWN || OWN[l]) {
         const double zl = (double)Z[l];
         acc0 += zl * (double)W[l];
         acc1 += zl * (double)R[l];
       }
     } else if constexpr (OP == V_DOT1) {
-      if (OWN[l]) acc0 += (double)R[l] * (double)R[l];
+      if (!OWN || OWN[l]) acc0 += (double)R[l] * (double)R[l];
     } else if constexpr (OP == V_RZ_JACOBI) {
       const T pz = DINV[l] * R[l];
       P[l] = pz;
-      if (OWN[l]) acc0 += (double)R[l] * (double)pz;
+      if (!OWN || OWN[l]) acc0 += (double)R[l] * (double)pz;
     } else if constexpr (OP == V_CHEB_INIT0) {
       const T d = c0 * DINV[l] * R[l];
       Dd[l] = d;
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
     } else if constexpr (OP == V_NORMALIZE) {
       X[l] = R[l] * scale;
     } else if constexpr (OP == V_TRUE_RES) {
-      if (OWN[l]) {
+      if (!OWN || OWN[l]) {
         const double e = (double)R[l] - (double)Tt[l];
         acc0 += e * e;
       }
@@ -675,7 +675,7 @@ __global__ __launch_bounds__(kXferThreads) void k_xfer(Table<XferArgs<Tf, Tc>> t
     if (e < a.E) {
       const int64_t g = e * C::S0 + r;
       if constexpr (DIR == 0) {
-        v = (Tf)gl(a.zc)[g];
+        v = (Tf)gl(a.zc)[a.umap_c ? (int64_t)gl(a.umap_c)[g] : g];
       } else {
         v = gl(a.rf)[g];
         if (a.tf) v -= gl(a.tf)[g];
@@ -737,6 +737,63 @@ void launch_xfer(int dir, int Nf, int Nc, const Table<XferArgs<Tf, Tc>>& t, int6
 template void launch_xfer<float, float>(int, int, int, const Table<XferArgs<float, float>>&, int64_t, const double*, hipStream_t);
 template void launch_xfer<float, double>(int, int, int, const Table<XferArgs<float, double>>&, int64_t, const double*, hipStream_t);
 template void launch_xfer<double, double>(int, int, int, const Table<XferArgs<double, double>>&, int64_t, const double*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// unique-DOF operators of an assembled level
+// ---------------------------------------------------------------------------
+constexpr int kSpThreads = 256;
+
+int64_t spmv_blocks(int64_t n) { return (n + kSpThreads - 1) / kSpThreads; }
+
+__global__ __launch_bounds__(kSpThreads) void k_spmv(Table<SpmvArgs> tab) {
+  __shared__ double s_red[kSpThreads / 64];
+  int lb;
+  const SpmvArgs a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  const int64_t r = (int64_t)lb * kSpThreads + threadIdx.x;
+  double d = 0.0;
+  if (r < a.n) {
+    const SEM_GLOBAL int* col = gl(a.col);
+    const SEM_GLOBAL double* val = gl(a.val);
+    const SEM_GLOBAL double* x = gl(a.x);
+    double y = 0.0;
+    for (int k = 0; k < a.W; ++k) y += val[k * a.n + r] * x[col[k * a.n + r]];
+    gl(a.y)[r] = y;
+    d = x[r] * y;
+  }
+  if (a.partial) {
+    const double s = block_sum<kSpThreads>(d, s_red);
+    if (threadIdx.x == 0) gl(a.partial)[lb] = s;
+  }
+}
+
+void launch_spmv(const Table<SpmvArgs>& t, int64_t total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL(k_spmv, dim3((unsigned)total_blocks), dim3(kSpThreads), 0, s, t);
+  SEM_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(kSpThreads) void k_usum(Table<UsumArgs> tab) {
+  int lb;
+  const UsumArgs a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  const int64_t r = (int64_t)lb * kSpThreads + threadIdx.x;
+  if (r >= a.n) return;
+  double s = 0.0;
+  if (!gl(a.udir)[r]) {
+    const SEM_GLOBAL int* idx = gl(a.idx);
+    const SEM_GLOBAL double* in = gl(a.in);
+    const int q1 = gl(a.off)[r + 1];
+    for (int q = gl(a.off)[r]; q < q1; ++q) s += in[idx[q]];
+  }
+  gl(a.out)[r] = s;
+}
+
+void launch_usum(const Table<UsumArgs>& t, int64_t total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL(k_usum, dim3((unsigned)total_blocks), dim3(kSpThreads), 0, s, t);
+  SEM_HIP(hipGetLastError());
+}
 
 // ---------------------------------------------------------------------------
 // setup kernels

@@ -57,7 +57,8 @@ void DevBuf::release() {
 
 int64_t MeshData::resident_bytes() const {
   const DevBuf* bufs[] = {&Dg64, &Dg32, &wg, &x, &y, &z, &gid, &dmask, &owner, &G64, &G32, &B64, &B32,
-                          &dinv64, &dinv32, &gs_off, &gs_idx, &gs_dir, &dir_idx};
+                          &dinv64, &dinv32, &gs_off, &gs_idx, &gs_dir, &dir_idx, &umap, &u2l_off, &u2l_idx,
+                          &udir, &dinv_u, &ell_col, &ell_val};
   int64_t s = 0;
   for (const DevBuf* b : bufs) s += (int64_t)b->bytes;
   return s;

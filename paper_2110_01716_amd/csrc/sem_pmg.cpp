@@ -260,6 +260,7 @@ extern "C" int sem_pmg_setup(sem_mesh mh, const sem_pmg_opts* oin, sem_pmg* out)
       SEM_HIP(hipStreamSynchronize(s));
       coarse_ids(Nf, Nc, f.E, gf, df, gc, dc);
       build_mesh(c, Nc, f.E, gc.data(), dc.data(), s);
+      if (l + 1 == P->n_levels) build_assembled(c, s);  // coarse solve on unique DOFs
       P->lv[l].mesh = cm;
       // prolongation J (fine x coarse) and restriction J^T for the pair (l-1, l)
       std::vector<double> J((Nf + 1) * (Nc + 1)), JT((Nc + 1) * (Nf + 1));
