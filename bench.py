@@ -38,6 +38,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per FP64 Ax launch (64^3, N=7) from rocprofv3 FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0 (scales from a plain 1 GiB copy), taken on the Ax kernel
+# whose source hashes to `source_sha16`; reported only while it still matches.
+AX_COUNTERS = {"source_sha16": "d96ce00e665e642c", "traffic_GB_per_launch": 8.590083,
+               "summary": "profiles/ax_64x64x64_N7_fp64_hbm_counters.txt"}
+
+
+def ax_source_sha16() -> str:
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2110_01716_amd", "csrc", "sem_kernels.hip")).read()
+    t = src[src.index("// ax-kernel-begin"):src.index("// ax-kernel-end")]
+    return hashlib.sha256(t.encode()).hexdigest()[:16]
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -288,7 +301,11 @@ def main():
         "ax": {"ms_mean": round(ms_avg, 4), "ms_median": round(ms_med, 4), "ms_min": round(min(ms), 4),
                "gdofs_kernel": round(dofs / (ms_avg * 1e-3) / 1e9, 3), "hbm_gbs": round(gbs, 1)},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": (AX_COUNTERS["traffic_GB_per_launch"]
+                                 if ax_source_sha16() == AX_COUNTERS["source_sha16"] else None),
+                     "traffic_unit": "GB per launch (algorithmic: %.3f)" % (bytes_per_launch / 1e9),
+                     "kernel": "k_ax<7,double>", "bytes_per_point": 64},
     }
     log("ax", res["ax"])
     if not a.no_solve:

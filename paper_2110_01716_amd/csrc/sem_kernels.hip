@@ -121,6 +121,7 @@ struct AxCfg {
   static constexpr int NPAD = NP | 1;  // odd row stride: conflict-free column reads
 };
 
+// ax-kernel-begin
 template <int N, typename T, bool HELM>
 __global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, const T* __restrict__ Dg) {
   using C = AxCfg<N>;
@@ -219,6 +220,8 @@ __global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, 
     if (tid == 0) gl(a.partial)[lb] = s;
   }
 }
+
+// ax-kernel-end
 
 int ax_blocks(int N, int64_t ne) {
   int epb = 1;
