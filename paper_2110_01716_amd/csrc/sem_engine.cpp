@@ -154,7 +154,7 @@ size_t layout(Slot& s, uint8_t* base) {
     }
   }
   s.stride = stride;
-  s.partial = (double*)take(8 * 2 * stride);
+  s.partial = (double*)take(8 * 3 * stride);  // [0], [1]: vector-kernel sums; [2]: Ax/SpMV sums read redundantly
   return off;
 }
 
@@ -309,7 +309,7 @@ class Plan {
   // y = A x on the unique DOFs of assembled level l (optionally the partials of x . y)
   template <typename FX, typename FY>
   void spmv(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, FX x_of, FY y_of, bool with_partial,
-            int skip_mode) {
+            int skip_mode, int region = 0) {
     std::vector<SpmvArgs> args;
     std::vector<int> starts{0};
     for (Slot* s : S) {
@@ -321,7 +321,7 @@ class Plan {
       a.val = m.ell_val.as<double>();
       a.x = x_of(*s);
       a.y = y_of(*s);
-      a.partial = with_partial ? s->partial : nullptr;
+      a.partial = with_partial ? s->partial + region * s->stride : nullptr;
       a.skip = skip(*s, skip_mode);
       args.push_back(a);
       starts.push_back(starts.back() + (int)spmv_blocks(a.n));
@@ -554,19 +554,25 @@ void Plan::build_vcycle(Group& g) {
     fin(g.cinit, S, FIN_RZ, 1, nvec, SK);
 
     if (U) {
-      spmv(g.citer, S, c, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2);
-      fin(g.citer, S, FIN_ALPHA, 1, [c](Slot& s) { return spmv_blocks(s.level(c).n_unique); }, 2);
+      // SpMV partials go to region 2; the update reduces them itself (no finalize launch)
+      spmv(g.citer, S, c, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2, 2);
     } else {
       apply_A<double>(g.citer, S, c, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2);
       fin(g.citer, S, FIN_ALPHA, 1, [c](Slot& s) { return (int64_t)ax_blocks(s.level(c).N, s.level(c).E); }, 2);
     }
-    vec<double>(g.citer, S, c, V_PCG_UPDATE, [cdinv](Slot& s, VecArgs<double>& a) {
+    vec<double>(g.citer, S, c, V_PCG_UPDATE, [cdinv, c, U](Slot& s, VecArgs<double>& a) {
       a.x = s.cx;
       a.p = s.cp;
       a.r = s.cr;
       a.w = s.cw;
       a.dinv = cdinv(s);
       a.scal = s.scal[1];
+      if (U) {
+        a.red_in = s.partial + 2 * s.stride;
+        a.red_n = spmv_blocks(s.level(c).n_unique);
+        a.scal_w = s.scal[1];
+        a.flags = s.flags[1];
+      }
     }, 2, U);
     fin(g.citer, S, FIN_CHECK_JACOBI, 1, nvec, 2, o.coarse_rtol,
         o.coarse_fixed_iters > 0 ? (1 << 30) : o.coarse_maxit, o.coarse_fixed_iters, true);

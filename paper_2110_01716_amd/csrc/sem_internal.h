@@ -211,6 +211,13 @@ struct VecArgs {
   double* partial = nullptr;  // [2][stride]
   int64_t stride = 0;
   double c0 = 0, c1 = 0, c2 = 0;
+  // V_PCG_UPDATE with red_in: every block sums red_in[0..red_n) (the Ax/SpMV
+  // partials of p . Ap) in the same fixed order and takes alpha = rz / sum
+  // itself, instead of a separate finalize launch (small problems only)
+  const double* red_in = nullptr;
+  int64_t red_n = 0;
+  double* scal_w = nullptr;   // where block 0 records pw and alpha
+  int* flags = nullptr;       // breakdown: status NaN, done
   Skip skip;
 };
 

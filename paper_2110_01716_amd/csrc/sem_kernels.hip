@@ -68,6 +68,18 @@ __device__ __forceinline__ bool skipped(const Skip& s) {
   return (s.f0 && *(volatile const SEM_GLOBAL int*)gl(s.f0)) || (s.f1 && *(volatile const SEM_GLOBAL int*)gl(s.f1));
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// For kernels whose neighbouring work items share cache lines (gather-scatter:
+// the copies of a face node live in adjacent elements), give every XCD one
+// contiguous range of logical blocks instead, so shared lines meet in one L2
+// (a bijection of [0, nblocks)).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = b % kXcds, slot = b / kXcds;
+  return x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
 // Barrier for LDS hand-offs only: unlike __syncthreads() it does not wait for
 // outstanding global loads, so an element's geometric factors stay in flight
 // across it. A one-wave workgroup needs no hardware barrier at all.
@@ -268,7 +280,7 @@ constexpr int kGsThreads = 128;
 template <typename T>
 __global__ __launch_bounds__(kGsThreads) void k_gs(Table<GsArgs<T>> tab) {
   int lb;
-  const GsArgs<T> a = fetch_args(tab, blockIdx.x, lb);
+  const GsArgs<T> a = fetch_args(tab, xcd_block(blockIdx.x, gridDim.x), lb);
   if (skipped(a.skip)) return;
   SEM_GLOBAL T* v = gl(a.v);
   const SEM_GLOBAL int* idx = gl(a.idx);
@@ -352,7 +364,33 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
   const int64_t base = (int64_t)lb * kVecThreads * per + threadIdx.x;
   double acc0 = 0.0, acc1 = 0.0;
   T alpha = 0, beta = 0, scale = 0;
-  if constexpr (OP == V_PCG_UPDATE) alpha = (T)gl(a.scal)[S_ALPHA];
+  if constexpr (OP == V_PCG_UPDATE) {
+    if (a.red_in) {
+      __shared__ double s_pw[kVecThreads / 64];
+      const SEM_GLOBAL double* ri = gl(a.red_in);
+      double v = 0.0;
+      for (int64_t k = threadIdx.x; k < a.red_n; k += kVecThreads) v += ri[k];
+      v = wave_sum(v);
+      if ((threadIdx.x & 63) == 0) s_pw[threadIdx.x >> 6] = v;
+      __syncthreads();
+      double pw = 0.0;
+      for (int w = 0; w < kVecThreads / 64; ++w) pw += s_pw[w];
+      double al = gl(a.scal)[S_RZ] / pw;
+      const bool bad = !isfinite(al);
+      if (bad) al = 0.0;
+      if (lb == 0 && threadIdx.x == 0) {
+        gl(a.scal_w)[S_PW] = pw;
+        gl(a.scal_w)[S_ALPHA] = al;
+        if (bad) {
+          gl(a.flags)[F_STATUS] = SEM_ENAN;
+          gl(a.flags)[F_DONE] = 1;
+        }
+      }
+      alpha = (T)al;
+    } else {
+      alpha = (T)gl(a.scal)[S_ALPHA];
+    }
+  }
   if constexpr (OP == V_P_JACOBI || OP == V_P_FLEX) beta = (T)gl(a.scal)[S_BETA];
   if constexpr (OP == V_NORMALIZE) scale = (T)gl(a.scal)[S_TMP];
   const T c0 = (T)a.c0, c1 = (T)a.c1, c2 = (T)a.c2;
@@ -744,28 +782,43 @@ template void launch_xfer<double, double>(int, int, int, const Table<XferArgs<do
 // ---------------------------------------------------------------------------
 // unique-DOF operators of an assembled level
 // ---------------------------------------------------------------------------
-constexpr int kSpThreads = 256;
+constexpr int kSpThreads = 64;
 
 int64_t spmv_blocks(int64_t n) { return (n + kSpThreads - 1) / kSpThreads; }
 
 __global__ __launch_bounds__(kSpThreads) void k_spmv(Table<SpmvArgs> tab) {
-  __shared__ double s_red[kSpThreads / 64];
   int lb;
   const SpmvArgs a = fetch_args(tab, blockIdx.x, lb);
   if (skipped(a.skip)) return;
   const int64_t r = (int64_t)lb * kSpThreads + threadIdx.x;
   double d = 0.0;
   if (r < a.n) {
-    const SEM_GLOBAL int* col = gl(a.col);
-    const SEM_GLOBAL double* val = gl(a.val);
+    const SEM_GLOBAL int* col = gl(a.col) + r;
+    const SEM_GLOBAL double* val = gl(a.val) + r;
     const SEM_GLOBAL double* x = gl(a.x);
+    // issue the row's (value, column) loads in groups of 9, then the gathers
     double y = 0.0;
-    for (int k = 0; k < a.W; ++k) y += val[k * a.n + r] * x[col[k * a.n + r]];
+    int k = 0;
+    for (; k + 9 <= a.W; k += 9) {
+      double v[9];
+      int c[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        v[q] = __builtin_nontemporal_load(val + (int64_t)(k + q) * a.n);
+        c[q] = __builtin_nontemporal_load(col + (int64_t)(k + q) * a.n);
+      }
+      double xv[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) xv[q] = x[c[q]];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) y += v[q] * xv[q];
+    }
+    for (; k < a.W; ++k) y += val[(int64_t)k * a.n] * x[col[(int64_t)k * a.n]];
     gl(a.y)[r] = y;
     d = x[r] * y;
   }
   if (a.partial) {
-    const double s = block_sum<kSpThreads>(d, s_red);
+    const double s = wave_sum(d);
     if (threadIdx.x == 0) gl(a.partial)[lb] = s;
   }
 }
