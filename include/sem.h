@@ -220,6 +220,10 @@ typedef struct {
   int32_t maxit;              /* outer iteration cap (10000)                    */
   int32_t check_every;        /* host polls convergence every k iters (1)       */
   int32_t fixed_iters;        /* > 0: exactly this many iterations, no test     */
+  double lambda;              /* Helmholtz shift: solve (A + lambda B) x = b, the
+                                 velocity-substep operator (Implementation,
+                                 Helmholtz paragraph); Jacobi-PCG only (the
+                                 hierarchy must be NULL); 0 = Poisson          */
 } sem_solve_opts;
 
 void sem_solve_opts_default(sem_solve_opts* o);

@@ -243,3 +243,24 @@ def scatter_unique(gid: np.ndarray, ids: np.ndarray, vals: np.ndarray) -> np.nda
 def assemble_rhs(N, B, gid, dirichlet, f):
     """b = M QQ^T (B f): weak form of a nodal source f."""
     return mask(dirichlet, gs(gid, B * f))
+
+
+# ---------------------------------------------------------------------------
+# Helmholtz (velocity substep operator, Implementation, Helmholtz paragraph)
+# ---------------------------------------------------------------------------
+
+def apply_H(N, G, B, lam, gid, dirichlet, u):
+    """M QQ^T (A_L + lam B) u on a consistent E-vector."""
+    return mask(dirichlet, gs(gid, helmholtz_local(N, G, B, lam, u)))
+
+
+def helmholtz_jacobi_inverse(N, G, B, lam, gid, dirichlet) -> np.ndarray:
+    """1 / diag(A + lam B) on consistent storage, 0 on Dirichlet nodes."""
+    d = gs(gid, diag_local(N, G) + lam * B)
+    return np.where(dirichlet != 0, 0.0, 1.0 / np.where(dirichlet != 0, 1.0, d))
+
+
+def assemble_helmholtz(N, G, B, lam, gid, dirichlet):
+    """Assembled A + lam diag(QQ^T B) on interior unique DOFs (tiny meshes)."""
+    A, ids, Bd = assemble(N, G, gid, dirichlet, B)
+    return (A + lam * sp.diags(Bd)).tocsr(), ids

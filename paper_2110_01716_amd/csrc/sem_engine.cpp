@@ -96,6 +96,7 @@ struct Slot {
        *lt[kMaxLevels] = {};
   double *cr = nullptr, *cx = nullptr, *cp = nullptr, *cw = nullptr;
   double* clocal = nullptr;  // restriction output on coarse element storage (assembled coarse level)
+  double* dinv_h = nullptr;  // Jacobi-PCG: inverse diagonal of A + lambda B (Helmholtz solves)
   double* partial = nullptr;
   int64_t stride = 0;
   int idx = -1;
@@ -106,6 +107,8 @@ struct Slot {
   int* flags[2] = {nullptr, nullptr};
 
   const MeshData& level(int l) const { return pmg ? pmg->lv[l].mesh->d : mesh->d; }
+  double lam() const { return pmg ? 0.0 : o.lambda; }
+  const double* dinv0() const { return lam() != 0.0 ? dinv_h : level(0).dinv64.as<double>(); }
   int nlev() const { return pmg ? pmg->n_levels : 1; }
   bool f32() const { return pmg && pmg->o.smoother_dtype == SEM_F32; }
 };
@@ -129,6 +132,7 @@ size_t layout(Slot& s, uint8_t* base) {
   s.z = (double*)take(8 * n0);
   s.p = (double*)take(8 * n0);
   s.w = (double*)take(8 * n0);
+  if (!s.pmg) s.dinv_h = (double*)take(8 * n0);
   if (s.pmg) {
     const int L = s.pmg->n_levels;
     const size_t ts = s.f32() ? 4 : 8;
@@ -243,6 +247,12 @@ class Plan {
         const MeshData& m = s->level(l);
         AxArgs<T> a;
         a.G = G_of<T>(m);
+        if constexpr (sizeof(T) == 8) {
+          if (l == 0 && s->lam() != 0.0) {
+            a.B = m.B64.as<double>();
+            a.lambda = s->lam();
+          }
+        }
         a.u = u_of(*s);
         a.Au = t_of(*s);
         a.e0 = 0;
@@ -254,8 +264,9 @@ class Plan {
       }
       const T* D = D_of<T>(kv.second[0]->level(l));
       const int64_t total = starts.back();
-      add(seq, args, starts, [N, D, total](const Table<AxArgs<T>>& t, hipStream_t st) {
-        launch_ax<T>(N, t, total, D, st);
+      const bool helm = args[0].B != nullptr;  // groups never mix Poisson and Helmholtz
+      add(seq, args, starts, [N, D, total, helm](const Table<AxArgs<T>>& t, hipStream_t st) {
+        launch_ax<T>(N, t, total, D, st, helm);
       });
     }
     gs<T>(seq, S, l, t_of, skip_mode);
@@ -653,14 +664,14 @@ void Plan::build_jacobi(Group& g) {
     a.p = s.p;
     a.r = s.r;
     a.w = s.w;
-    a.dinv = s.level(0).dinv64.as<double>();
+    a.dinv = s.dinv0();
     a.scal = s.scal[0];
   }, 1);
   fin(h, S, FIN_CHECK_JACOBI, 0, [](Slot& s) { return vec_blocks(s.level(0).nloc); }, 1);
   vec<double>(h, S, 0, V_P_JACOBI, [](Slot& s, VecArgs<double>& a) {
     a.p = s.p;
     a.r = s.r;
-    a.dinv = s.level(0).dinv64.as<double>();
+    a.dinv = s.dinv0();
     a.scal = s.scal[0];
   }, 1);
 }
@@ -683,7 +694,7 @@ void Plan::build_init(Group& g) {
     vec<double>(q, S, 0, V_RZ_JACOBI, [](Slot& s, VecArgs<double>& a) {
       a.r = s.r;
       a.p = s.p;
-      a.dinv = s.level(0).dinv64.as<double>();
+      a.dinv = s.dinv0();
     }, 1);
     fin(q, S, FIN_RZ, 0, [](Slot& s) { return vec_blocks(s.level(0).nloc); }, 1);
   }
@@ -691,7 +702,7 @@ void Plan::build_init(Group& g) {
 
 // group slots by solver structure
 static std::string signature(const Slot& s) {
-  if (!s.pmg) return "jacobi";
+  if (!s.pmg) return s.lam() != 0.0 ? "jacobi-helmholtz" : "jacobi";
   const sem_pmg_opts& o = s.pmg->o;
   char buf[128];
   snprintf(buf, sizeof(buf), "pmg L%d t%d k%d pre%d post%d cf%d cm%d cc%d", s.pmg->n_levels, (int)o.smoother_dtype,
@@ -806,7 +817,7 @@ static void run_body(sem_batch_s* B, Plan& P) {
 
 static double true_relres(Slot& s, hipStream_t st) {
   const MeshData& m = s.level(0);
-  apply_A(m, SEM_F64, s.x, s.w, st);
+  apply_H(m, s.lam(), s.x, s.w, st);
   Table<VecArgs<double>> t;
   t.one.n = m.nloc;
   t.one.r = const_cast<double*>(s.b);
@@ -840,12 +851,16 @@ static void batch_add(sem_batch_s* B, sem_mesh m, sem_pmg p, const double* b, do
   sem_solve_opts_default(&s.o);
   if (oin) s.o = *oin;
   if (!(s.o.rtol >= 0)) fail(SEM_EINVAL, "batch add: rtol must be >= 0");
+  if (p && s.o.lambda != 0.0)
+    fail(SEM_EINVAL, "batch add: Helmholtz (lambda != 0) is solved by Jacobi-PCG; pass no pMG hierarchy");
+  if (!std::isfinite(s.o.lambda) || s.o.lambda < 0.0) fail(SEM_EINVAL, "batch add: lambda must be finite and >= 0");
   if (s.o.maxit < 1) s.o.maxit = 1;
   if (s.o.check_every < 1) s.o.check_every = 1;
   const size_t bytes = layout(s, nullptr);
   s.ws = pool_get(bytes);
   s.ws_bytes = bytes;
   layout(s, static_cast<uint8_t*>(s.ws));
+  if (s.lam() != 0.0) helmholtz_dinv(s.level(0), s.lam(), s.dinv_h, s.w, B->stream);
   s.state = 1;
   s.info = sem_solve_info{};
   s.info.status = 1;
@@ -944,6 +959,7 @@ extern "C" void sem_solve_opts_default(sem_solve_opts* o) {
   o->maxit = 10000;
   o->check_every = 1;
   o->fixed_iters = 0;
+  o->lambda = 0.0;
 }
 
 extern "C" size_t sem_solve_workspace_bytes(sem_mesh m, sem_pmg p) {

@@ -184,6 +184,7 @@ enum VecOp : int {
   V_TRUE_RES,         // partial0 = own (r - t).(r - t)
   V_DIV_DINV,         // x = r / dinv (0 where dinv = 0)
   V_SCALE,            // x = c0 r
+  V_AXPY,             // x += c0 r
   V_COUNT
 };
 
@@ -300,8 +301,10 @@ int64_t gs_blocks(int64_t n_shared, int64_t n_dir);
 int xfer_blocks(int Nf, int Nc, int64_t E);
 constexpr int kFinThreads = 1024;
 
+// helm: the table's problems carry B and lambda (Helmholtz (A_L + lambda B) u)
 template <typename T>
-void launch_ax(int N, const Table<AxArgs<T>>& t, int64_t total_blocks, const T* D, hipStream_t s);
+void launch_ax(int N, const Table<AxArgs<T>>& t, int64_t total_blocks, const T* D, hipStream_t s,
+               bool helm = false);
 template <typename T>
 void launch_gs(const Table<GsArgs<T>>& t, int64_t total_blocks, hipStream_t s);
 template <typename T>
@@ -321,6 +324,8 @@ void launch_geometry(const MeshData& m, double* detmin_partial, double* vol_part
                      hipStream_t s);
 void launch_diag_local(const MeshData& m, double* dl, hipStream_t s);
 void launch_dinv_finish(const MeshData& m, const double* d_assembled, hipStream_t s);
+// out = 0 on Dirichlet copies, else 1 / d
+void launch_dinv_to(const MeshData& m, const double* d_assembled, double* out, hipStream_t s);
 void launch_tensor_coords(int Nf, int Nc, int64_t E, const double* in, double* out, const double* Jcf,
                           hipStream_t s);
 void launch_start_vector(int64_t n, const int64_t* gid, const uint8_t* dmask, double* v, hipStream_t s);
@@ -340,6 +345,10 @@ double mesh_dot(const MeshData& m, sem_dtype t, const void* a, const void* b, hi
 
 // single-problem helpers used by setup code
 void apply_A(const MeshData& m, sem_dtype t, const void* u, void* Au, hipStream_t s);
+// (M QQ^T (A_L + lambda B)) u in FP64
+void apply_H(const MeshData& m, double lambda, const double* u, double* Hu, hipStream_t s);
+// inverse Jacobi diagonal of M QQ^T (A_L + lambda B) into out (FP64), using tmp [nloc]
+void helmholtz_dinv(const MeshData& m, double lambda, double* out, double* tmp, hipStream_t s);
 
 }  // namespace sem
 

@@ -249,9 +249,9 @@ int ax_blocks(int N, int64_t ne) {
 }
 
 template <typename T>
-void launch_ax(int N, const Table<AxArgs<T>>& t, int64_t total_blocks, const T* D, hipStream_t s) {
+void launch_ax(int N, const Table<AxArgs<T>>& t, int64_t total_blocks, const T* D, hipStream_t s, bool helm) {
   if (total_blocks <= 0) return;
-  const bool helm = t.many == nullptr && t.one.B != nullptr;
+  if (t.many == nullptr && t.one.B != nullptr) helm = true;
   switch (N) {
 #define SEM_AX_CASE(n)                                                                        \
   case n:                                                                                     \
@@ -269,8 +269,8 @@ void launch_ax(int N, const Table<AxArgs<T>>& t, int64_t total_blocks, const T* 
   }
   SEM_HIP(hipGetLastError());
 }
-template void launch_ax<double>(int, const Table<AxArgs<double>>&, int64_t, const double*, hipStream_t);
-template void launch_ax<float>(int, const Table<AxArgs<float>>&, int64_t, const float*, hipStream_t);
+template void launch_ax<double>(int, const Table<AxArgs<double>>&, int64_t, const double*, hipStream_t, bool);
+template void launch_ax<float>(int, const Table<AxArgs<float>>&, int64_t, const float*, hipStream_t, bool);
 
 // ---------------------------------------------------------------------------
 // gather-scatter
@@ -461,6 +461,8 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
       X[l] = DINV[l] != T(0) ? R[l] / DINV[l] : T(0);
     } else if constexpr (OP == V_SCALE) {
       X[l] = c0 * R[l];
+    } else if constexpr (OP == V_AXPY) {
+      X[l] += c0 * R[l];
     }
   }
   constexpr bool RED = (OP == V_PCG_UPDATE || OP == V_DOT2 || OP == V_DOT1 || OP == V_RZ_JACOBI ||
@@ -490,7 +492,7 @@ void launch_vec(VecOp op, const Table<VecArgs<T>>& t, int64_t total_blocks, hipS
     SEM_VEC_CASE(V_CHEB_INIT0) SEM_VEC_CASE(V_CHEB_INITX) SEM_VEC_CASE(V_CHEB_STEP0)
     SEM_VEC_CASE(V_CHEB_STEP) SEM_VEC_CASE(V_ZERO) SEM_VEC_CASE(V_COPY)
     SEM_VEC_CASE(V_SCALE_DINV) SEM_VEC_CASE(V_NORMALIZE) SEM_VEC_CASE(V_TRUE_RES)
-    SEM_VEC_CASE(V_DIV_DINV) SEM_VEC_CASE(V_SCALE)
+    SEM_VEC_CASE(V_DIV_DINV) SEM_VEC_CASE(V_SCALE) SEM_VEC_CASE(V_AXPY)
 #undef SEM_VEC_CASE
     default:
       fail(SEM_EINVAL, "unknown vector op %d", (int)op);
@@ -976,6 +978,18 @@ __global__ __launch_bounds__(256) void k_dinv(int64_t nloc, const double* __rest
   const double v = dmask[l] ? 0.0 : 1.0 / d[l];
   inv64[l] = v;
   inv32[l] = (float)v;
+}
+
+__global__ __launch_bounds__(256) void k_dinv_to(int64_t nloc, const double* __restrict__ d,
+                                                 const uint8_t* __restrict__ dmask, double* out) {
+  const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (l < nloc) out[l] = dmask[l] ? 0.0 : 1.0 / d[l];
+}
+
+void launch_dinv_to(const MeshData& m, const double* d_assembled, double* out, hipStream_t s) {
+  const int64_t nb = (m.nloc + 255) / 256;
+  hipLaunchKernelGGL(k_dinv_to, dim3((unsigned)nb), dim3(256), 0, s, m.nloc, d_assembled, m.dmask.as<uint8_t>(), out);
+  SEM_HIP(hipGetLastError());
 }
 
 void launch_dinv_finish(const MeshData& m, const double* d_assembled, hipStream_t s) {

@@ -115,6 +115,24 @@ void apply_A(const MeshData& m, sem_dtype t, const void* u, void* Au, hipStream_
   }
 }
 
+void apply_H(const MeshData& m, double lambda, const double* u, double* Hu, hipStream_t s) {
+  ax_range<double>(m, u, Hu, 0, m.E, lambda != 0.0 ? m.B64.as<double>() : nullptr, lambda, nullptr, s);
+  gs_apply<double>(m, Hu, 1, s);
+}
+
+void helmholtz_dinv(const MeshData& m, double lambda, double* out, double* tmp, hipStream_t s) {
+  // local diagonal of A^e + lambda B, summed over copies, inverted, masked
+  launch_diag_local(m, tmp, s);
+  Table<VecArgs<double>> t;
+  t.one.n = m.nloc;
+  t.one.x = tmp;
+  t.one.r = const_cast<double*>(m.B64.as<double>());
+  t.one.c0 = lambda;
+  launch_vec<double>(V_AXPY, t, vec_blocks(m.nloc), s);
+  gs_apply<double>(m, tmp, 0, s);
+  launch_dinv_to(m, tmp, out, s);
+}
+
 double mesh_dot(const MeshData& m, sem_dtype t, const void* a, const void* b, hipStream_t s) {
   const int64_t nb = vec_blocks(m.nloc);
   DevBuf part;

@@ -55,7 +55,7 @@ class sem_pmg_info(C.Structure):
 
 class sem_solve_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
-                ("fixed_iters", C.c_int32)]
+                ("fixed_iters", C.c_int32), ("lam", C.c_double)]
 
 
 class sem_solve_info(C.Structure):
@@ -291,10 +291,11 @@ def sem_pmg_apply(h, r, z, stream=None):
 
 
 def solve_opts(**kw) -> sem_solve_opts:
+    """sem_solve_opts with defaults; `lam` (or `lambda_`) is the Helmholtz shift."""
     o = sem_solve_opts()
     load().sem_solve_opts_default(C.byref(o))
     for k, v in kw.items():
-        setattr(o, k, v)
+        setattr(o, "lam" if k in ("lam", "lambda_", "helmholtz_lambda") else k, v)
     return o
 
 

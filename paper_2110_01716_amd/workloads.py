@@ -41,6 +41,7 @@ __all__ = [
     "random_rhs",
     "manufactured_source",
     "manufactured_solution",
+    "manufactured_neumann_solution",
     "relabel",
     "config_meshes",
     "batched_problem_specs",
@@ -196,6 +197,11 @@ def random_rhs(mesh: BoxMesh, seed: int) -> np.ndarray:
 def manufactured_solution(mesh: BoxMesh) -> np.ndarray:
     """u = sin(pi x) sin(pi y) sin(pi z) at the nodes (zero on the unit cube's faces)."""
     return np.sin(np.pi * mesh.x) * np.sin(np.pi * mesh.y) * np.sin(np.pi * mesh.z)
+
+
+def manufactured_neumann_solution(mesh: BoxMesh) -> np.ndarray:
+    """u = cos(pi x) cos(pi y) cos(pi z): zero normal derivative on the unit cube's faces."""
+    return np.cos(np.pi * mesh.x) * np.cos(np.pi * mesh.y) * np.cos(np.pi * mesh.z)
 
 
 def manufactured_source(mesh: BoxMesh) -> np.ndarray:
