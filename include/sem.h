@@ -235,6 +235,8 @@ typedef struct {
   double relres_true;         /* ||b - A x|| / ||b|| recomputed at exit         */
   int64_t coarse_iters;       /* total coarse-grid PCG iterations               */
   double seconds;             /* wall time of the solve call                    */
+  double relres_initial;      /* ||b - A x0|| / ||b|| of the starting guess: 1
+                                 for x0 = 0, smaller after projection           */
 } sem_solve_info;
 
 /* Solves A x = b, A the assembled masked SEM Laplacian, with Jacobi-PCG
@@ -256,6 +258,34 @@ int sem_pcg_solve_batched(int n, const sem_mesh* m, const sem_pmg* p, const doub
 
 /* Device bytes a solve on (m, p) allocates for its vectors. */
 size_t sem_solve_workspace_bytes(sem_mesh m, sem_pmg p);
+
+/* ------------------------------------------------------------------------ */
+/* Projection onto prior solutions (Implementation, "Projection Is Key")     */
+/* ------------------------------------------------------------------------ */
+
+/* A space of up to L_max earlier solutions kept A-orthonormal on the device
+ * (P and AP, 2 (L_max + 1) FP64 E-vectors). For a new b the best approximation in
+ * the A-norm is xbar = P P^T b (one multi-dot); the Krylov solver then solves
+ * A dx = b - A xbar; dx is A-orthogonalised against P by one round of
+ * classical Gram-Schmidt (one multi-dot) and appended. When the space is full
+ * it restarts from the latest solution alone. */
+typedef struct sem_proj_s* sem_proj;
+int sem_proj_create(sem_mesh m, int L_max, sem_proj* out);
+int sem_proj_destroy(sem_proj pr);
+/* Number of vectors currently in the space. */
+int sem_proj_size(sem_proj pr, int* L);
+/* Empties the space. */
+int sem_proj_reset(sem_proj pr);
+/* Exports basis vector i (device FP64 [E][Np] buffers p and Ap, either may be
+ * NULL). SEM_EINVAL if i >= size. Asynchronous. */
+int sem_proj_export(sem_proj pr, int i, double* p, double* Ap, void* stream);
+
+/* sem_pcg_solve with the projected starting guess; the residual test stays
+ * relative to ||b||; info->relres_initial reports the projected residual.
+ * The solution is then added to the space. The mesh must be the one the
+ * space was created on. */
+int sem_pcg_solve_projected(sem_proj pr, sem_pmg p, const double* b, double* x, const sem_solve_opts* o,
+                            sem_solve_info* info, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Continuous batching: solves join and leave at iteration boundaries        */

@@ -864,6 +864,7 @@ static void batch_add(sem_batch_s* B, sem_mesh m, sem_pmg p, const double* b, do
   s.state = 1;
   s.info = sem_solve_info{};
   s.info.status = 1;
+  s.info.relres_initial = 1.0;  // x0 = 0
   s.t0 = Clock::now();
   SEM_HIP(hipMemsetAsync(s.scal[0], 0, sizeof(double) * 2 * S_COUNT, B->stream));
   SEM_HIP(hipMemsetAsync(s.flags[0], 0, sizeof(int) * 2 * F_COUNT, B->stream));

@@ -292,6 +292,27 @@ struct UsumArgs {
   Skip skip;
 };
 
+// multi-dot: partial[k][blk] = sum over owned points of v[k] . y (k < K)
+struct MdotArgs {
+  int64_t n = 0;
+  int K = 0;
+  const double* const* v = nullptr;  // device array of K vector pointers
+  const double* y = nullptr;
+  const uint8_t* owner = nullptr;
+  double* partial = nullptr;         // [K][stride]
+  int64_t stride = 0;
+};
+// out = scale * (a0 y + sign sum_k coef[k] v[k]), coef on the device
+struct LincombArgs {
+  int64_t n = 0;
+  int K = 0;
+  const double* const* v = nullptr;
+  const double* coef = nullptr;
+  const double* y = nullptr;
+  double a0 = 0, sign = 1, scale = 1;
+  double* out = nullptr;
+};
+
 // ---------------------------------------------------------------------------
 // launchers (defined in sem_kernels.hip)
 // ---------------------------------------------------------------------------
@@ -313,6 +334,9 @@ template <typename Tin, typename Tout>
 void launch_cast(const Table<CastArgs<Tin, Tout>>& t, int64_t total_blocks, hipStream_t s);
 void launch_fin(FinOp op, const Table<FinArgs>& t, int nprob, hipStream_t s);
 int64_t spmv_blocks(int64_t n);
+void launch_mdot(const MdotArgs& a, hipStream_t s);            // grid: vec_blocks(n) x ceil(K/8)
+void launch_mfin(const double* partial, int64_t stride, int64_t nblk, int K, double* out, hipStream_t s);
+void launch_lincomb(const LincombArgs& a, hipStream_t s);
 void launch_spmv(const Table<SpmvArgs>& t, int64_t total_blocks, hipStream_t s);
 void launch_usum(const Table<UsumArgs>& t, int64_t total_blocks, hipStream_t s);
 template <typename Tf, typename Tc>

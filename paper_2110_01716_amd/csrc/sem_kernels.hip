@@ -854,6 +854,95 @@ void launch_usum(const Table<UsumArgs>& t, int64_t total_blocks, hipStream_t s) 
 }
 
 // ---------------------------------------------------------------------------
+// projection space: multi-dot, per-component reduction, linear combination
+// ---------------------------------------------------------------------------
+constexpr int kMdotKC = 8;  // components per block (blockIdx.y picks the group)
+
+__global__ __launch_bounds__(kVecThreads) void k_mdot(MdotArgs a) {
+  __shared__ double s_red[kMdotKC][kVecThreads / 64];
+  const int k0 = blockIdx.y * kMdotKC;
+  const int per = vec_per(a.n);
+  const int64_t base = (int64_t)blockIdx.x * kVecThreads * per + threadIdx.x;
+  const SEM_GLOBAL double* Y = gl(a.y);
+  const SEM_GLOBAL uint8_t* OWN = gl(a.owner);
+  double acc[kMdotKC];
+#pragma unroll
+  for (int c = 0; c < kMdotKC; ++c) acc[c] = 0.0;
+  for (int q = 0; q < per; ++q) {
+    const int64_t l = base + (int64_t)q * kVecThreads;
+    if (l >= a.n) break;
+    if (!OWN[l]) continue;
+    const double y = Y[l];
+#pragma unroll
+    for (int c = 0; c < kMdotKC; ++c)
+      if (k0 + c < a.K) acc[c] += gl(gl(a.v)[k0 + c])[l] * y;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < kMdotKC; ++c) {
+    const double sc = wave_sum(acc[c]);
+    if (lane == 0) s_red[c][wid] = sc;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMdotKC && k0 + (int)threadIdx.x < a.K) {
+    double t = 0.0;
+    for (int w = 0; w < kVecThreads / 64; ++w) t += s_red[threadIdx.x][w];
+    gl(a.partial)[(int64_t)(k0 + threadIdx.x) * a.stride + blockIdx.x] = t;
+  }
+}
+
+void launch_mdot(const MdotArgs& a, hipStream_t s) {
+  if (a.K <= 0 || a.n <= 0) return;
+  const dim3 g((unsigned)vec_blocks(a.n), (unsigned)((a.K + kMdotKC - 1) / kMdotKC));
+  hipLaunchKernelGGL(k_mdot, g, dim3(kVecThreads), 0, s, a);
+  SEM_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_mfin(const double* __restrict__ partial, int64_t stride,
+                                                      int64_t nblk, double* out) {
+  __shared__ double s_red[kFinThreads / 64];
+  const SEM_GLOBAL double* part = gl(partial) + (int64_t)blockIdx.x * stride;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int64_t k = threadIdx.x;
+  for (; k + 3 * kFinThreads < nblk; k += 4 * kFinThreads) {
+    a0 += part[k];
+    a1 += part[k + kFinThreads];
+    a2 += part[k + 2 * kFinThreads];
+    a3 += part[k + 3 * kFinThreads];
+  }
+  for (; k < nblk; k += kFinThreads) a0 += part[k];
+  const double s = wave_sum((a0 + a1) + (a2 + a3));
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kFinThreads / 64; ++w) t += s_red[w];
+    gl(out)[blockIdx.x] = t;
+  }
+}
+
+void launch_mfin(const double* partial, int64_t stride, int64_t nblk, int K, double* out, hipStream_t s) {
+  if (K <= 0) return;
+  hipLaunchKernelGGL(k_mfin, dim3(K), dim3(kFinThreads), 0, s, partial, stride, nblk, out);
+  SEM_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_lincomb(LincombArgs a) {
+  const int64_t l = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (l >= a.n) return;
+  double v = a.y ? a.a0 * gl(a.y)[l] : 0.0;
+  double s = 0.0;
+  for (int k = 0; k < a.K; ++k) s += gl(a.coef)[k] * gl(gl(a.v)[k])[l];
+  gl(a.out)[l] = a.scale * (v + a.sign * s);
+}
+
+void launch_lincomb(const LincombArgs& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((a.n + kVecThreads - 1) / kVecThreads)), dim3(kVecThreads), 0, s, a);
+  SEM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // setup kernels
 // ---------------------------------------------------------------------------
 

@@ -60,7 +60,8 @@ class sem_solve_opts(C.Structure):
 
 class sem_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double),
-                ("relres_true", C.c_double), ("coarse_iters", C.c_int64), ("seconds", C.c_double)]
+                ("relres_true", C.c_double), ("coarse_iters", C.c_int64), ("seconds", C.c_double),
+                ("relres_initial", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -98,6 +99,12 @@ _SIGS = {
     "sem_batch_step": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int)]),
     "sem_batch_poll": (C.c_int, [_P, C.c_int, C.POINTER(sem_solve_info)]),
     "sem_batch_release": (C.c_int, [_P, C.c_int]),
+    "sem_proj_create": (C.c_int, [_P, C.c_int, C.POINTER(_P)]),
+    "sem_proj_destroy": (C.c_int, [_P]),
+    "sem_proj_size": (C.c_int, [_P, C.POINTER(C.c_int)]),
+    "sem_proj_reset": (C.c_int, [_P]),
+    "sem_proj_export": (C.c_int, [_P, C.c_int, _P, _P, _P]),
+    "sem_pcg_solve_projected": (C.c_int, [_P, _P, _P, _P, C.POINTER(sem_solve_opts), C.POINTER(sem_solve_info), _P]),
     "sem_status_string": (C.c_char_p, [C.c_int]),
     "sem_last_error": (C.c_char_p, []),
 }
@@ -361,6 +368,41 @@ def sem_batch_release(h, slot: int):
     _check(load().sem_batch_release(h, slot), "sem_batch_release")
 
 
+def sem_proj_create(mesh, L_max: int):
+    h = C.c_void_p()
+    _check(load().sem_proj_create(mesh, L_max, C.byref(h)), "sem_proj_create")
+    return h
+
+
+def sem_proj_destroy(h):
+    _check(load().sem_proj_destroy(h), "sem_proj_destroy")
+
+
+def sem_proj_size(h) -> int:
+    n = C.c_int(0)
+    _check(load().sem_proj_size(h, C.byref(n)), "sem_proj_size")
+    return n.value
+
+
+def sem_proj_reset(h):
+    _check(load().sem_proj_reset(h), "sem_proj_reset")
+
+
+def sem_proj_export(h, i, p=None, Ap=None, stream=None):
+    _check(load().sem_proj_export(h, i, _ptr(p), _ptr(Ap), _stream(stream)), "sem_proj_export")
+
+
+def sem_pcg_solve_projected(proj, pmg, b, x, opts: sem_solve_opts | None = None, stream=None, check=True) -> dict:
+    info = sem_solve_info()
+    rc = load().sem_pcg_solve_projected(proj, pmg, _ptr(b), _ptr(x), C.byref(opts) if opts is not None else None,
+                                        C.byref(info), _stream(stream))
+    if check and rc != SEM_OK:
+        _check(rc, "sem_pcg_solve_projected")
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
+
+
 def sem_status_string(code: int) -> str:
     return load().sem_status_string(code).decode()
 
@@ -412,6 +454,40 @@ class Pmg:
     def close(self):
         if self.h is not None:
             sem_pmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Projection:
+    """Space of earlier solutions on one mesh (sem_proj_*)."""
+
+    def __init__(self, mesh: Mesh, L_max: int = 30):
+        self.mesh = mesh
+        self.L_max = L_max
+        self.h = sem_proj_create(mesh.h, L_max)
+
+    @property
+    def size(self) -> int:
+        return sem_proj_size(self.h)
+
+    def reset(self):
+        sem_proj_reset(self.h)
+
+    def solve(self, pmg, b, x, opts: sem_solve_opts | None = None, stream=None, check=True) -> dict:
+        return sem_pcg_solve_projected(self.h, pmg.h if isinstance(pmg, Pmg) else pmg, b, x, opts,
+                                       stream=stream, check=check)
+
+    def export(self, i, p=None, Ap=None, stream=None):
+        sem_proj_export(self.h, i, p, Ap, stream)
+
+    def close(self):
+        if self.h is not None:
+            sem_proj_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -46,6 +46,7 @@ __all__ = [
     "config_meshes",
     "batched_problem_specs",
     "serving_mesh_sides",
+    "rhs_sequence",
 ]
 
 
@@ -192,6 +193,30 @@ def random_rhs(mesh: BoxMesh, seed: int) -> np.ndarray:
     b = vals[inv.reshape(mesh.gid.shape)]
     b = np.where(mesh.dirichlet != 0, 0.0, b)
     return np.ascontiguousarray(b, dtype=np.float64)
+
+
+def rhs_sequence(mesh: BoxMesh, steps: int, *, modes: int = 6, noise: float = 1e-3,
+                 dt: float = 0.05, seed: int = 0) -> list:
+    """Right-hand sides b^m, m = 0..steps-1, that vary smoothly in time.
+
+    b^m = sum_k cos(omega_k m dt + phi_k) g_k + noise * eta^m: `modes` fixed
+    random fields g_k (random_rhs with seeds derived from `seed`) with
+    amplitudes that oscillate at omega_k ~ U(0.5, 2), phi_k ~ U(0, 2 pi), plus
+    a fresh random field eta^m of relative size `noise` at every step. This
+    stands in for the pressure right-hand sides of successive time steps,
+    which lie close to a low-dimensional space.
+    """
+    rng = np.random.default_rng(seed)
+    omega = rng.uniform(0.5, 2.0, size=modes)
+    phi = rng.uniform(0.0, 2.0 * np.pi, size=modes)
+    g = [random_rhs(mesh, 7919 * seed + k + 1) for k in range(modes)]
+    out = []
+    for m in range(steps):
+        b = noise * random_rhs(mesh, 104729 * seed + 100003 + m)
+        for k in range(modes):
+            b = b + np.cos(omega[k] * m * dt + phi[k]) * g[k]
+        out.append(np.ascontiguousarray(b))
+    return out
 
 
 def manufactured_solution(mesh: BoxMesh) -> np.ndarray:
