@@ -20,6 +20,9 @@ The same line reports:
     and for FP64 flexible CG preconditioned by the FP32 p-multigrid V-cycle
     (N = 7 -> 3 -> 1, Chebyshev-Jacobi degree 2, coarse FP64 Jacobi-PCG to
     1e-2) on the 48^3 mesh (and the 64^3 mesh with --solve-c2);
+  * projection onto prior solutions: per-solve time and iterations of the
+    pMG solve over a sequence of 40 smoothly varying right-hand sides on the
+    48^3 mesh for L_max = 0, 8 and 30;
   * cpu_baseline: the FP64 NumPy oracle's Ax on a bounded sample of the same
     workload on the host cores.
 """
@@ -116,6 +119,46 @@ def solve_pair(sem, bm, m, label, skip_pcg=False):
     log(label, "pcg", out["pcg_fp64"])
     out["speedup_pmg_vs_pcg"] = out["pcg_fp64"]["seconds"] / out["pmg_fp32"]["seconds"]
     out["rel_diff_pmg_vs_pcg"] = float((xp - x).abs().max() / x.abs().max())
+    p.close()
+    return out
+
+
+def bench_projection(sem, bm, m, steps=40, lmaxes=(0, 8, 30)):
+    """Successive right-hand sides (smooth in time, 8 modes + 1e-3 rough
+    noise, dt = 0.05) solved to 1e-8 by flexible CG + pMG, with the starting
+    guess projected onto the last L_max solutions; L_max = 0 is the plain
+    solve. Reports per-solve time and iterations averaged over all steps."""
+    import torch
+    from paper_2110_01716_amd import workloads as wl
+    at = wl.rhs_sequence_fn(bm, modes=8, noise=1e-3, dt=0.05, seed=4000, device="cuda")
+    p = sem.Pmg(m)
+    opts = sem.solve_opts(rtol=1e-8)
+    x = torch.empty(bm.x.shape, dtype=torch.float64, device="cuda")
+    sem.sem_pcg_solve(m.h, p.h, at(0), x, opts)  # warm
+    out = {"steps": steps, "rhs": "8 smooth modes + 1e-3 rough noise, dt 0.05", "rtol": 1e-8}
+    for L in lmaxes:
+        pr = sem.Projection(m, L) if L else None
+        secs, its, rel0, worst = [], [], [], 0.0
+        for k in range(steps):
+            b = at(k)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = pr.solve(p, b, x, opts) if pr else sem.sem_pcg_solve(m.h, p.h, b, x, opts)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t)
+            its.append(info["iters"])
+            rel0.append(info["relres_initial"])
+            worst = max(worst, info["relres_true"])
+            del b
+        out[f"L{L}"] = {"s_per_solve": round(float(np.mean(secs)), 5), "iters_mean": round(float(np.mean(its)), 2),
+                        "iters_last10": its[-10:], "relres_initial_median": float(np.median(rel0)),
+                        "relres_true_max": worst}
+        log("projection", L, out[f"L{L}"])
+        if pr:
+            pr.close()
+    base = out["L0"]["s_per_solve"]
+    for L in lmaxes[1:]:
+        out[f"speedup_L{L}_vs_L0"] = round(base / out[f"L{L}"]["s_per_solve"], 3)
     p.close()
     return out
 
@@ -237,6 +280,8 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--skip-pcg", action="store_true", help="time only the pMG solve")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-projection", action="store_true")
+    ap.add_argument("--projection-only", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--serving-only", action="store_true")
@@ -267,6 +312,10 @@ def main():
         return
     if a.serving_only:
         print(json.dumps({"serving": bench_serving(sem)}), flush=True)
+        return
+    if a.projection_only:
+        bm3, m3 = build_mesh(sem, wl.config_meshes()["pmg_48x48x48_N7"])
+        print(json.dumps({"projection": bench_projection(sem, bm3, m3)}), flush=True)
         return
     if a.solve_only:
         spec3 = wl.config_meshes()["pmg_48x48x48_N7"]
@@ -317,6 +366,8 @@ def main():
         spec3 = wl.config_meshes()["pmg_48x48x48_N7"]
         bm3, m3 = build_mesh(sem, spec3)
         poisson["48x48x48_N7"] = solve_pair(sem, bm3, m3, "c3", a.skip_pcg)
+        if not a.no_projection:
+            poisson["48x48x48_N7"]["projection"] = bench_projection(sem, bm3, m3)
         m3.close()
         res["poisson"] = poisson
     if not a.no_batched:

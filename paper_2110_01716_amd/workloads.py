@@ -47,6 +47,7 @@ __all__ = [
     "batched_problem_specs",
     "serving_mesh_sides",
     "rhs_sequence",
+    "rhs_sequence_fn",
 ]
 
 
@@ -195,28 +196,60 @@ def random_rhs(mesh: BoxMesh, seed: int) -> np.ndarray:
     return np.ascontiguousarray(b, dtype=np.float64)
 
 
-def rhs_sequence(mesh: BoxMesh, steps: int, *, modes: int = 6, noise: float = 1e-3,
-                 dt: float = 0.05, seed: int = 0) -> list:
-    """Right-hand sides b^m, m = 0..steps-1, that vary smoothly in time.
+def rhs_sequence_fn(mesh: BoxMesh, *, modes: int = 6, noise: float = 1e-3, dt: float = 0.05,
+                    seed: int = 0, device=None):
+    """Right-hand sides b^m that vary smoothly in time, as a function m -> b^m.
 
-    b^m = sum_k cos(omega_k m dt + phi_k) g_k + noise * eta^m: `modes` fixed
-    random fields g_k (random_rhs with seeds derived from `seed`) with
-    amplitudes that oscillate at omega_k ~ U(0.5, 2), phi_k ~ U(0, 2 pi), plus
-    a fresh random field eta^m of relative size `noise` at every step. This
-    stands in for the pressure right-hand sides of successive time steps,
-    which lie close to a low-dimensional space.
+    b^m = keep * (sum_k cos(omega_k m dt + phi_k) g_k + noise * eta^m), where
+    keep is 0 on Dirichlet nodes and 1 elsewhere and
+      g_k   = sin(pi a_k1 x + c_k1) sin(pi a_k2 y + c_k2) sin(pi a_k3 z + c_k3),
+              a ~ U{1..4}, c ~ U(0, 2 pi): `modes` fixed smooth fields;
+      omega_k ~ U(0.5, 2), phi_k ~ U(0, 2 pi);
+      eta^m = sin(q_1 x + s_1) sin(q_2 y + s_2) sin(q_3 z + s_3) with
+              q ~ U(100, 300), s ~ U(0, 2 pi) drawn afresh for every step from
+              default_rng([seed, m]): a rough field outside the smooth span.
+    All values are functions of the node coordinates, so every copy of a shared
+    node gets the same value (the vector is consistent). This stands in for
+    the pressure right-hand sides of successive time steps, which lie close to
+    a low-dimensional space. device=None evaluates with numpy; otherwise with
+    torch on that device (for large meshes).
     """
     rng = np.random.default_rng(seed)
     omega = rng.uniform(0.5, 2.0, size=modes)
     phi = rng.uniform(0.0, 2.0 * np.pi, size=modes)
-    g = [random_rhs(mesh, 7919 * seed + k + 1) for k in range(modes)]
-    out = []
-    for m in range(steps):
-        b = noise * random_rhs(mesh, 104729 * seed + 100003 + m)
+    wave = rng.integers(1, 5, size=(modes, 3))
+    shift = rng.uniform(0.0, 2.0 * np.pi, size=(modes, 3))
+    if device is None:
+        sin = np.sin
+        X, Y, Z = mesh.x, mesh.y, mesh.z
+        keep = (mesh.dirichlet == 0).astype(np.float64)
+    else:
+        import torch
+        sin = torch.sin
+        X, Y, Z = (torch.from_numpy(a).to(device) for a in (mesh.x, mesh.y, mesh.z))
+        keep = torch.from_numpy(mesh.dirichlet == 0).to(device=device, dtype=torch.float64)
+
+    def field(a, c):
+        return sin(a[0] * X + c[0]) * sin(a[1] * Y + c[1]) * sin(a[2] * Z + c[2])
+
+    g = [keep * field(np.pi * wave[k], shift[k]) for k in range(modes)]
+
+    def at(m: int):
+        r = np.random.default_rng([seed, m])
+        eta = field(r.uniform(100.0, 300.0, size=3), r.uniform(0.0, 2.0 * np.pi, size=3))
+        b = noise * keep * eta
         for k in range(modes):
-            b = b + np.cos(omega[k] * m * dt + phi[k]) * g[k]
-        out.append(np.ascontiguousarray(b))
-    return out
+            b = b + float(np.cos(omega[k] * m * dt + phi[k])) * g[k]
+        return b
+
+    return at
+
+
+def rhs_sequence(mesh: BoxMesh, steps: int, *, modes: int = 6, noise: float = 1e-3,
+                 dt: float = 0.05, seed: int = 0) -> list:
+    """[b^0, .., b^(steps-1)] of rhs_sequence_fn, as numpy arrays."""
+    at = rhs_sequence_fn(mesh, modes=modes, noise=noise, dt=dt, seed=seed)
+    return [np.ascontiguousarray(at(m)) for m in range(steps)]
 
 
 def manufactured_solution(mesh: BoxMesh) -> np.ndarray:

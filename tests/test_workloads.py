@@ -59,3 +59,23 @@ def test_named_workloads():
     specs = wl.batched_problem_specs()
     assert len(specs) == 256 and {s["N"] for s in specs} == {5, 7, 9}
     assert wl.serving_mesh_sides() == [8, 10, 12, 14, 17, 19, 21, 23, 25, 27, 29, 31, 34, 36, 38, 40]
+
+
+def test_rhs_sequence_consistent_masked_and_device_path():
+    import torch
+    m = wl.box_mesh(3, 2, 2, N=4, deform=0.05, seed=3)
+    seq = wl.rhs_sequence(m, 3, modes=4, noise=1e-2, seed=5)
+    order = np.argsort(m.gid.ravel(), kind="stable")
+    for b in seq:
+        v = b.ravel()[order]
+        g = m.gid.ravel()[order]
+        same = g[1:] == g[:-1]
+        assert np.all(v[1:][same] == v[:-1][same])  # every copy of a node equal
+        assert np.all(b[m.dirichlet != 0] == 0)
+        assert np.max(np.abs(b)) > 0.1
+    at = wl.rhs_sequence_fn(m, modes=4, noise=1e-2, seed=5, device="cpu")
+    for k, b in enumerate(seq):
+        assert np.max(np.abs(at(k).numpy() - b)) <= 1e-13
+    # consecutive steps are close, distant ones are not
+    d1 = np.max(np.abs(seq[1] - seq[0]))
+    assert d1 < 0.5 * np.max(np.abs(seq[0]))
