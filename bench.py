@@ -20,6 +20,8 @@ The same line reports:
     and for FP64 flexible CG preconditioned by the FP32 p-multigrid V-cycle
     (N = 7 -> 3 -> 1, Chebyshev-Jacobi degree 2, coarse FP64 Jacobi-PCG to
     1e-2) on the 48^3 mesh (and the 64^3 mesh with --solve-c2);
+  * the Helmholtz operator (A_L + lambda B) u (72 B per point) on the same
+    mesh, and Helmholtz Jacobi-PCG solves on the 48^3 mesh;
   * projection onto prior solutions: per-solve time and iterations of the
     pMG solve over a sequence of 40 smoothly varying right-hand sides on the
     48^3 mesh for L_max = 0, 8 and 30;
@@ -70,18 +72,26 @@ def build_mesh(sem, spec):
     return bm, m
 
 
-def time_ax(sem, m, E, Np, steps, warmup):
+def time_ax(sem, m, E, Np, steps, warmup, lam=None):
+    """Event-timed FP64 Ax (lam=None) or Helmholtz (A_L + lam B) u launches."""
     import torch
     u = torch.rand((E, Np), dtype=torch.float64, device="cuda") * 2 - 1
     Au = torch.empty_like(u)
+
+    def op():
+        if lam is None:
+            sem.sem_ax(m.h, u, Au)
+        else:
+            sem.sem_helmholtz(m.h, u, Au, lam)
+
     for _ in range(warmup):
-        sem.sem_ax(m.h, u, Au)
+        op()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for a, b in ev:
         a.record()
-        sem.sem_ax(m.h, u, Au)
+        op()
         b.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -160,6 +170,28 @@ def bench_projection(sem, bm, m, steps=40, lmaxes=(0, 8, 30)):
     for L in lmaxes[1:]:
         out[f"speedup_L{L}_vs_L0"] = round(base / out[f"L{L}"]["s_per_solve"], 3)
     p.close()
+    return out
+
+
+def bench_helmholtz_solve(sem, bm, m, lams=(1e2, 1e4)):
+    """FP64 Jacobi-PCG on (A + lam B) x = b (the velocity-substep operator) to 1e-8."""
+    import torch
+    from paper_2110_01716_amd import workloads as wl
+    b = torch.from_numpy(wl.random_rhs(bm, 2001)).to("cuda")
+    x = torch.empty_like(b)
+    out = {}
+    for lam in lams:
+        o = sem.solve_opts(rtol=1e-8, maxit=20000, lam=lam)
+        sem.sem_pcg_solve(m.h, None, b, x, o)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = sem.sem_pcg_solve(m.h, None, b, x, o)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        out[f"lambda_{lam:g}"] = {"seconds": round(sec, 5), "iters": info["iters"],
+                                  "ms_per_iter": round(sec / max(info["iters"], 1) * 1e3, 4),
+                                  "relres_true": info["relres_true"]}
+        log("helmholtz-pcg", lam, out[f"lambda_{lam:g}"])
     return out
 
 
@@ -357,6 +389,13 @@ def main():
                      "kernel": "k_ax<7,double>", "bytes_per_point": 64},
     }
     log("ax", res["ax"])
+    hw, hms = time_ax(sem, m, E, Np, a.steps, a.warmup, lam=10.0)
+    hms_avg = float(np.mean(hms))
+    hgbs = 72 * E * Np / (hms_avg * 1e-3) / 1e9
+    res["helmholtz_ax"] = {"ms_mean": round(hms_avg, 4), "ms_median": round(float(np.median(hms)), 4),
+                           "hbm_gbs": round(hgbs, 1), "frac": round(hgbs / HBM_PEAK_GBS, 4), "bytes_per_point": 72,
+                           "kernel": "k_ax<7,double,helmholtz>"}
+    log("helmholtz ax", res["helmholtz_ax"])
     if not a.no_solve:
         poisson = {}
         if a.solve_c2:
@@ -366,6 +405,7 @@ def main():
         spec3 = wl.config_meshes()["pmg_48x48x48_N7"]
         bm3, m3 = build_mesh(sem, spec3)
         poisson["48x48x48_N7"] = solve_pair(sem, bm3, m3, "c3", a.skip_pcg)
+        poisson["48x48x48_N7"]["helmholtz_jacobi_pcg"] = bench_helmholtz_solve(sem, bm3, m3)
         if not a.no_projection:
             poisson["48x48x48_N7"]["projection"] = bench_projection(sem, bm3, m3)
         m3.close()

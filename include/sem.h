@@ -259,6 +259,19 @@ int sem_pcg_solve_batched(int n, const sem_mesh* m, const sem_pmg* p, const doub
 /* Device bytes a solve on (m, p) allocates for its vectors. */
 size_t sem_solve_workspace_bytes(sem_mesh m, sem_pmg p);
 
+/* Solves A x = b (or (A + lambda B) x = b with the Jacobi preconditioner)
+ * by right-preconditioned flexible GMRES(K) (Implementation, FlexCG/GMRES
+ * paragraph; Performance Results, GMRES with K <= 6): preconditioner one pMG
+ * V-cycle (p != NULL) or Jacobi (p == NULL). Each Arnoldi step takes one
+ * round of classical Gram-Schmidt with a single multi-dot; the least-squares
+ * residual (Givens rotations) is the convergence test; after K steps without
+ * convergence it restarts from the true residual. K in [1, 64]; o->maxit
+ * bounds the total number of steps, o->fixed_iters runs exactly that many.
+ * b, x: device FP64 [E][Np], consistent and masked; x0 = 0. Device memory:
+ * 2K + 2 FP64 E-vectors from the workspace pool. Errors as sem_pcg_solve. */
+int sem_gmres_solve(sem_mesh m, sem_pmg p, int K, const double* b, double* x, const sem_solve_opts* o,
+                    sem_solve_info* info, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Projection onto prior solutions (Implementation, "Projection Is Key")     */
 /* ------------------------------------------------------------------------ */

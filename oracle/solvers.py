@@ -14,6 +14,9 @@ over unique DOFs (operators.dot). Operators are passed as callables v -> A v.
   with a short recurrence (Implementation, FlexCG/GMRES paragraph). The
   Polak-Ribiere form beta = (z_new, r_new - r_old) / (z_old, r_old)
   (Notay 2000) is used.
+* Flexible GMRES(K): the alternative outer solver (same paragraph; GMRES
+  with K bounded by 6 in Performance Results), right-preconditioned so the
+  preconditioner may vary between steps.
 * Chebyshev acceleration of point Jacobi (Implementation, pMG smoothers;
   Saad, Alg. 12.1) on the interval [lo rho, hi rho] of D^-1 A.
 * Power iteration for rho = lambda_max(D^-1 A).
@@ -98,6 +101,60 @@ def flexcg(apply_A, apply_M, dot, b, rtol=1e-8, maxit=1000, fixed_iters=None):
         beta = dot(z, r - r_old) / rz
         rz = dot(r, z)
         p = z + beta * p
+    return SolveResult(x, it, relres, hist)
+
+
+def fgmres(apply_A, apply_M, dot, b, K, rtol=1e-8, maxit=1000, fixed_iters=None):
+    """Right-preconditioned flexible GMRES(K) with x0 = 0 (Saad 1993).
+
+    Arnoldi on v_0 = b / |b|: z_j = M(v_j), w = A z_j, h_ij = (v_i, w) for
+    i <= j (classical Gram-Schmidt: every coefficient against the same w),
+    h_{j+1,j} = |w - sum_i h_ij v_i|, v_{j+1} = that vector / h_{j+1,j}.
+    The iterate x = x_start + Z y with y minimising |beta e_1 - H y| (a
+    library least-squares solve of the (j+2) x (j+1) Hessenberg matrix); that
+    minimum is the residual norm used for the stopping test. After K steps the
+    method restarts from the true residual b - A x. hist[j] is the relative
+    least-squares residual after step j + 1.
+    """
+    x = np.zeros_like(b)
+    bnorm = np.sqrt(dot(b, b))
+    hist = []
+    if bnorm == 0.0:
+        return SolveResult(x, 0, 0.0, hist)
+    limit = fixed_iters if fixed_iters is not None else maxit
+    it = 0
+    r = b.copy()
+    relres = 1.0
+    while True:
+        beta = np.sqrt(dot(r, r))
+        V = [r / beta]
+        Z = []
+        H = np.zeros((K + 1, K))
+        y = np.zeros(0)
+        stop = False
+        for j in range(K):
+            Z.append(apply_M(V[j]))
+            w = apply_A(Z[j])
+            h = [dot(V[i], w) for i in range(j + 1)]
+            for i in range(j + 1):
+                w = w - h[i] * V[i]
+            H[: j + 1, j] = h
+            H[j + 1, j] = np.sqrt(dot(w, w))
+            V.append(w / H[j + 1, j] if H[j + 1, j] > 0 else w)
+            e1 = np.zeros(j + 2)
+            e1[0] = beta
+            y = np.linalg.lstsq(H[: j + 2, : j + 1], e1, rcond=None)[0]
+            relres = np.linalg.norm(e1 - H[: j + 2, : j + 1] @ y) / bnorm
+            hist.append(relres)
+            it += 1
+            if it >= limit or (fixed_iters is None and relres <= rtol) or H[j + 1, j] == 0:
+                stop = True
+                break
+        for i in range(len(y)):
+            x = x + y[i] * Z[i]
+        if stop:
+            break
+        r = b - apply_A(x)
     return SolveResult(x, it, relres, hist)
 
 

@@ -42,9 +42,8 @@ using Clock = std::chrono::steady_clock;
 // ---------------------------------------------------------------------------
 // workspace pool: reuse freed solve workspaces (no allocation on the hot path)
 // ---------------------------------------------------------------------------
-namespace {
-std::mutex g_pool_mu;
-std::multimap<size_t, void*> g_pool;
+static std::mutex g_pool_mu;
+static std::multimap<size_t, void*> g_pool;
 
 void* pool_get(size_t bytes) {
   {
@@ -78,7 +77,6 @@ void pool_put(void* p, size_t bytes) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
   g_pool.emplace(bytes, p);
 }
-}  // namespace
 
 // ---------------------------------------------------------------------------
 // slots
@@ -1073,26 +1071,57 @@ extern "C" int sem_pcg_solve_batched(int n, const sem_mesh* m, const sem_pmg* p,
   return g != SEM_OK ? g : rc;
 }
 
+namespace sem {
+
+// a one-slot batch whose plan is the V-cycle alone
+struct VcycleRunner {
+  sem_batch_s B;
+  std::unique_ptr<Plan> P;
+  sem_pmg p = nullptr;
+};
+
+VcycleRunner* vcycle_runner_create(sem_pmg p, hipStream_t st) {
+  auto v = std::make_unique<VcycleRunner>();
+  v->p = p;
+  batch_init(&v->B, 1, st);
+  Slot& s = v->B.slots[0];
+  s.mesh = p->base;
+  s.pmg = p;
+  const size_t bytes = layout(s, nullptr);
+  s.ws = pool_get(bytes);
+  s.ws_bytes = bytes;
+  layout(s, static_cast<uint8_t*>(s.ws));
+  s.state = 2;
+  std::vector<Slot*> one{&s};
+  v->P = make_plan(one, false, true, st);
+  return v.release();
+}
+
+// the V-cycle reads slot.r and writes slot.z: copy r in, z out
+void vcycle_runner_apply(VcycleRunner* v, const double* r, double* z) {
+  Slot& s = v->B.slots[0];
+  const size_t bytes = sizeof(double) * v->p->base->d.nloc;
+  SEM_HIP(hipMemcpyAsync(s.r, r, bytes, hipMemcpyDeviceToDevice, v->B.stream));
+  run_body(&v->B, *v->P);
+  SEM_HIP(hipMemcpyAsync(z, s.z, bytes, hipMemcpyDeviceToDevice, v->B.stream));
+}
+
+int64_t vcycle_runner_coarse_iters(VcycleRunner* v) {
+  fetch_ctrl(&v->B);
+  return host_flags(&v->B, 0, 0)[F_TOTAL];
+}
+
+void vcycle_runner_destroy(VcycleRunner* v) { delete v; }
+
+}  // namespace sem
+
 extern "C" int sem_pmg_apply(sem_pmg p, const double* r, double* z, void* stream) {
   return guarded([&] {
     if (!p || !r || !z) fail(SEM_EINVAL, "sem_pmg_apply: NULL argument");
-    sem_batch_s B;
-    batch_init(&B, 1, (hipStream_t)stream);
-    Slot& s = B.slots[0];
-    s.mesh = p->base;
-    s.pmg = p;
-    const size_t bytes = layout(s, nullptr);
-    s.ws = pool_get(bytes);
-    s.ws_bytes = bytes;
-    layout(s, static_cast<uint8_t*>(s.ws));
-    s.state = 2;
-    // the V-cycle reads slot.r and writes slot.z: copy r in, z out
-    SEM_HIP(hipMemcpyAsync(s.r, r, sizeof(double) * p->base->d.nloc, hipMemcpyDeviceToDevice, B.stream));
-    std::vector<Slot*> one{&s};
-    auto P = make_plan(one, false, true, B.stream);
-    run_body(&B, *P);
-    SEM_HIP(hipMemcpyAsync(z, s.z, sizeof(double) * p->base->d.nloc, hipMemcpyDeviceToDevice, B.stream));
-    SEM_HIP(hipStreamSynchronize(B.stream));
+    std::unique_ptr<VcycleRunner, void (*)(VcycleRunner*)> v(vcycle_runner_create(p, (hipStream_t)stream),
+                                                              vcycle_runner_destroy);
+    vcycle_runner_apply(v.get(), r, z);
+    SEM_HIP(hipStreamSynchronize((hipStream_t)stream));
   });
 }
 

@@ -373,6 +373,29 @@ void apply_A(const MeshData& m, sem_dtype t, const void* u, void* Au, hipStream_
 void apply_H(const MeshData& m, double lambda, const double* u, double* Hu, hipStream_t s);
 // inverse Jacobi diagonal of M QQ^T (A_L + lambda B) into out (FP64), using tmp [nloc]
 void helmholtz_dinv(const MeshData& m, double lambda, double* out, double* tmp, hipStream_t s);
+// FP64 unique-DOF inner product with caller scratch partial [2 * vec_blocks(nloc)]
+double mesh_dot_ws(const MeshData& m, const double* a, const double* b, double* partial, hipStream_t s);
+// out[k] = (v_k, y) over unique DOFs for k < K; v is a device array of K
+// vector pointers; partial [K][stride] scratch, stride >= vec_blocks(nloc)
+void mesh_multidot(const MeshData& m, const double* const* v, int K, const double* y, double* partial,
+                   int64_t stride, double* out, hipStream_t s);
+// out = scale (a0 y + sign sum_{k<K} coef[k] v_k), coef on the device; out may alias y or v_k
+void mesh_lincomb(const MeshData& m, const double* const* v, int K, const double* coef, const double* y, double a0,
+                  double sign, double scale, double* out, hipStream_t s);
+// single-vector FP64 update x <- op(x, r, c0) over n entries (V_SCALE, V_AXPY, V_SCALE_DINV, ...)
+void vec_op1(VecOp op, int64_t n, double* x, const double* r, double c0, const double* dinv, hipStream_t s);
+
+// workspace pool shared by all solves (reuses freed device blocks)
+void* pool_get(size_t bytes);
+void pool_put(void* p, size_t bytes);
+
+// One pMG V-cycle z = M(r) on FP64 consistent E-vectors, with the solver
+// engine's plan built once and reused across applications.
+struct VcycleRunner;
+VcycleRunner* vcycle_runner_create(sem_pmg p, hipStream_t s);
+void vcycle_runner_apply(VcycleRunner* v, const double* r, double* z);
+int64_t vcycle_runner_coarse_iters(VcycleRunner* v);
+void vcycle_runner_destroy(VcycleRunner* v);
 
 }  // namespace sem
 

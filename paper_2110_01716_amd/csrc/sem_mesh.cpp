@@ -133,6 +133,64 @@ void helmholtz_dinv(const MeshData& m, double lambda, double* out, double* tmp, 
   launch_dinv_to(m, tmp, out, s);
 }
 
+double mesh_dot_ws(const MeshData& m, const double* a, const double* b, double* partial, hipStream_t s) {
+  const int64_t nb = vec_blocks(m.nloc);
+  Table<VecArgs<double>> tb;
+  tb.one.n = m.nloc;
+  tb.one.z = const_cast<double*>(a);
+  tb.one.w = const_cast<double*>(b);
+  tb.one.r = const_cast<double*>(b);
+  tb.one.owner = m.owner.as<uint8_t>();
+  tb.one.partial = partial;
+  tb.one.stride = nb;
+  launch_vec<double>(V_DOT2, tb, nb, s);
+  std::vector<double> h(nb);
+  SEM_HIP(hipMemcpyAsync(h.data(), partial, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  double sum = 0.0;
+  for (int64_t k = 0; k < nb; ++k) sum += h[k];
+  return sum;
+}
+
+void mesh_multidot(const MeshData& m, const double* const* v, int K, const double* y, double* partial,
+                   int64_t stride, double* out, hipStream_t s) {
+  MdotArgs a;
+  a.n = m.nloc;
+  a.K = K;
+  a.v = v;
+  a.y = y;
+  a.owner = m.owner.as<uint8_t>();
+  a.partial = partial;
+  a.stride = stride;
+  launch_mdot(a, s);
+  launch_mfin(partial, stride, vec_blocks(m.nloc), K, out, s);
+}
+
+void mesh_lincomb(const MeshData& m, const double* const* v, int K, const double* coef, const double* y, double a0,
+                  double sign, double scale, double* out, hipStream_t s) {
+  LincombArgs a;
+  a.n = m.nloc;
+  a.K = K;
+  a.v = v;
+  a.coef = coef;
+  a.y = y;
+  a.a0 = a0;
+  a.sign = sign;
+  a.scale = scale;
+  a.out = out;
+  launch_lincomb(a, s);
+}
+
+void vec_op1(VecOp op, int64_t n, double* x, const double* r, double c0, const double* dinv, hipStream_t s) {
+  Table<VecArgs<double>> t;
+  t.one.n = n;
+  t.one.x = x;
+  t.one.r = const_cast<double*>(r);
+  t.one.dinv = dinv;
+  t.one.c0 = c0;
+  launch_vec<double>(op, t, vec_blocks(n), s);
+}
+
 double mesh_dot(const MeshData& m, sem_dtype t, const void* a, const void* b, hipStream_t s) {
   const int64_t nb = vec_blocks(m.nloc);
   DevBuf part;

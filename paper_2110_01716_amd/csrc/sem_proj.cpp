@@ -36,51 +36,22 @@ struct sem_proj_s {
   std::vector<double> hbeta;         // host copy of beta
 };
 
-namespace sem {
 namespace {
 
-// out[k] = (p_k, y) over unique DOFs, k < K (device array)
-void multidot(sem_proj_s* pr, const DevBuf& ptrs, int K, const double* y, double* out, hipStream_t s) {
-  const MeshData& m = pr->m->d;
-  MdotArgs a;
-  a.n = m.nloc;
-  a.K = K;
-  a.v = ptrs.as<const double*>();
-  a.y = y;
-  a.owner = m.owner.as<uint8_t>();
-  a.partial = pr->partial.as<double>();
-  a.stride = pr->stride;
-  launch_mdot(a, s);
-  launch_mfin(pr->partial.as<double>(), pr->stride, vec_blocks(m.nloc), K, out, s);
+void multidot(sem_proj_s* pr, const sem::DevBuf& ptrs, int K, const double* y, double* out, hipStream_t s) {
+  sem::mesh_multidot(pr->m->d, ptrs.as<const double*>(), K, y, pr->partial.as<double>(), pr->stride, out, s);
 }
 
-// out = scale (a0 y + sign sum_{k<K} coef[k] v_k)
-void lincomb(sem_proj_s* pr, const DevBuf& ptrs, int K, const double* coef, const double* y, double a0,
+void lincomb(sem_proj_s* pr, const sem::DevBuf& ptrs, int K, const double* coef, const double* y, double a0,
              double sign, double scale, double* out, hipStream_t s) {
-  LincombArgs a;
-  a.n = pr->m->d.nloc;
-  a.K = K;
-  a.v = ptrs.as<const double*>();
-  a.coef = coef;
-  a.y = y;
-  a.a0 = a0;
-  a.sign = sign;
-  a.scale = scale;
-  a.out = out;
-  launch_lincomb(a, s);
+  sem::mesh_lincomb(pr->m->d, ptrs.as<const double*>(), K, coef, y, a0, sign, scale, out, s);
 }
 
-void vec1(VecOp op, int64_t n, double* x, const double* r, double c0, hipStream_t s) {
-  Table<VecArgs<double>> t;
-  t.one.n = n;
-  t.one.x = x;
-  t.one.r = const_cast<double*>(r);
-  t.one.c0 = c0;
-  launch_vec<double>(op, t, vec_blocks(n), s);
+void vec1(sem::VecOp op, int64_t n, double* x, const double* r, double c0, hipStream_t s) {
+  sem::vec_op1(op, n, x, r, c0, nullptr, s);
 }
 
 }  // namespace
-}  // namespace sem
 
 using namespace sem;
 
@@ -166,7 +137,7 @@ extern "C" int sem_pcg_solve_projected(sem_proj pr, sem_pmg pm, const double* b,
     double* alpha = pr->coef.as<double>();
     double* beta = alpha + pr->Lmax + 1;
     double* r = pr->r.as<double>();
-    const double bb = mesh_dot(m, SEM_F64, b, b, s);
+    const double bb = mesh_dot_ws(m, b, b, pr->partial.as<double>(), s);
     // starting guess xbar = P (P^T b), residual r = b - AP (P^T b)
     if (L > 0) {
       multidot(pr, pr->ptrP, L, b, alpha, s);
@@ -176,7 +147,7 @@ extern "C" int sem_pcg_solve_projected(sem_proj pr, sem_pmg pm, const double* b,
       SEM_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
       SEM_HIP(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     }
-    const double rr = mesh_dot(m, SEM_F64, r, r, s);
+    const double rr = mesh_dot_ws(m, r, r, pr->partial.as<double>(), s);
     const double rel0 = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     sem_solve_info inner{};
     bool solved = false;
@@ -212,7 +183,7 @@ extern "C" int sem_pcg_solve_projected(sem_proj pr, sem_pmg pm, const double* b,
         vec1(V_SCALE, n, r, r, -1.0, s);
         vec1(V_AXPY, n, r, b, 1.0, s);
         vec1(V_AXPY, n, r, w, 1.0, s);
-        const double xAx = mesh_dot(m, SEM_F64, x, r, s);
+        const double xAx = mesh_dot_ws(m, x, r, pr->partial.as<double>(), s);
         if (xAx > 0 && std::isfinite(xAx)) {
           const double inv = 1.0 / std::sqrt(xAx);
           vec1(V_SCALE, n, pr->P[0].as<double>(), x, inv, s);

@@ -99,6 +99,7 @@ _SIGS = {
     "sem_batch_step": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int)]),
     "sem_batch_poll": (C.c_int, [_P, C.c_int, C.POINTER(sem_solve_info)]),
     "sem_batch_release": (C.c_int, [_P, C.c_int]),
+    "sem_gmres_solve": (C.c_int, [_P, _P, C.c_int, _P, _P, C.POINTER(sem_solve_opts), C.POINTER(sem_solve_info), _P]),
     "sem_proj_create": (C.c_int, [_P, C.c_int, C.POINTER(_P)]),
     "sem_proj_destroy": (C.c_int, [_P]),
     "sem_proj_size": (C.c_int, [_P, C.POINTER(C.c_int)]),
@@ -366,6 +367,17 @@ def sem_batch_poll(h, slot: int) -> dict:
 
 def sem_batch_release(h, slot: int):
     _check(load().sem_batch_release(h, slot), "sem_batch_release")
+
+
+def sem_gmres_solve(mesh, pmg, K, b, x, opts: sem_solve_opts | None = None, stream=None, check=True) -> dict:
+    info = sem_solve_info()
+    rc = load().sem_gmres_solve(mesh, pmg, int(K), _ptr(b), _ptr(x), C.byref(opts) if opts is not None else None,
+                                C.byref(info), _stream(stream))
+    if check and rc != SEM_OK:
+        _check(rc, "sem_gmres_solve")
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
 
 
 def sem_proj_create(mesh, L_max: int):
