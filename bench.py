@@ -117,6 +117,14 @@ def solve_pair(sem, bm, m, label, skip_pcg=False):
     out["pmg_fp32"] = {"seconds": time.perf_counter() - t, "iters": info["iters"], "relres": info["relres"],
                        "relres_true": info["relres_true"], "coarse_iters": info["coarse_iters"]}
     log(label, "pmg", out["pmg_fp32"])
+    sem.sem_gmres_solve(m.h, p.h, 6, b, x, sem.solve_opts(rtol=1e-8))  # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    info = sem.sem_gmres_solve(m.h, p.h, 6, b, x, sem.solve_opts(rtol=1e-8))
+    torch.cuda.synchronize()
+    out["pmg_fp32_gmres6"] = {"seconds": time.perf_counter() - t, "iters": info["iters"], "relres": info["relres"],
+                              "relres_true": info["relres_true"], "coarse_iters": info["coarse_iters"]}
+    log(label, "pmg-gmres6", out["pmg_fp32_gmres6"])
     if skip_pcg:
         p.close()
         return out
@@ -133,7 +141,7 @@ def solve_pair(sem, bm, m, label, skip_pcg=False):
     return out
 
 
-def bench_projection(sem, bm, m, steps=40, lmaxes=(0, 8, 30)):
+def bench_projection(sem, bm, m, steps=40, lmaxes=(0, 8, 30), gmres_K=6):
     """Successive right-hand sides (smooth in time, 8 modes + 1e-3 rough
     noise, dt = 0.05) solved to 1e-8 by flexible CG + pMG, with the starting
     guess projected onto the last L_max solutions; L_max = 0 is the plain
@@ -146,8 +154,9 @@ def bench_projection(sem, bm, m, steps=40, lmaxes=(0, 8, 30)):
     x = torch.empty(bm.x.shape, dtype=torch.float64, device="cuda")
     sem.sem_pcg_solve(m.h, p.h, at(0), x, opts)  # warm
     out = {"steps": steps, "rhs": "8 smooth modes + 1e-3 rough noise, dt 0.05", "rtol": 1e-8}
-    for L in lmaxes:
-        pr = sem.Projection(m, L) if L else None
+    runs = [(L, 0) for L in lmaxes] + [(lmaxes[-1], gmres_K)]
+    for L, K in runs:
+        pr = sem.Projection(m, L, gmres_K=K) if L else None
         secs, its, rel0, worst = [], [], [], 0.0
         for k in range(steps):
             b = at(k)
@@ -160,15 +169,18 @@ def bench_projection(sem, bm, m, steps=40, lmaxes=(0, 8, 30)):
             rel0.append(info["relres_initial"])
             worst = max(worst, info["relres_true"])
             del b
-        out[f"L{L}"] = {"s_per_solve": round(float(np.mean(secs)), 5), "iters_mean": round(float(np.mean(its)), 2),
+        key = f"L{L}" + (f"_gmres{K}" if K else "")
+        out[key] = {"s_per_solve": round(float(np.mean(secs)), 5), "iters_mean": round(float(np.mean(its)), 2),
                         "iters_last10": its[-10:], "relres_initial_median": float(np.median(rel0)),
                         "relres_true_max": worst}
-        log("projection", L, out[f"L{L}"])
+        log("projection", key, out[key])
         if pr:
             pr.close()
     base = out["L0"]["s_per_solve"]
     for L in lmaxes[1:]:
         out[f"speedup_L{L}_vs_L0"] = round(base / out[f"L{L}"]["s_per_solve"], 3)
+    kg = f"L{lmaxes[-1]}_gmres{gmres_K}"
+    out[f"speedup_{kg}_vs_L0"] = round(base / out[kg]["s_per_solve"], 3)
     p.close()
     return out
 

@@ -289,6 +289,9 @@ int sem_proj_destroy(sem_proj pr);
 int sem_proj_size(sem_proj pr, int* L);
 /* Empties the space. */
 int sem_proj_reset(sem_proj pr);
+/* Inner solver of sem_pcg_solve_projected: K = 0 (default) the CG family of
+ * sem_pcg_solve, K > 0 flexible GMRES(K) as sem_gmres_solve. */
+int sem_proj_set_gmres(sem_proj pr, int K);
 /* Exports basis vector i (device FP64 [E][Np] buffers p and Ap, either may be
  * NULL). SEM_EINVAL if i >= size. Asynchronous. */
 int sem_proj_export(sem_proj pr, int i, double* p, double* Ap, void* stream);

@@ -27,6 +27,7 @@ struct sem_proj_s {
   sem_mesh m = nullptr;
   int Lmax = 0;
   int L = 0;
+  int gmres_K = 0;                   // inner solver: 0 = CG family, K > 0 = flexible GMRES(K)
   std::vector<sem::DevBuf> P, AP;    // L_max + 1 slots each
   sem::DevBuf ptrP, ptrAP;           // device arrays of the slot pointers
   sem::DevBuf coef;                  // device: alpha [L_max+1], beta [L_max+1]
@@ -107,6 +108,14 @@ extern "C" int sem_proj_reset(sem_proj pr) {
   });
 }
 
+extern "C" int sem_proj_set_gmres(sem_proj pr, int K) {
+  return guarded([&] {
+    if (!pr) fail(SEM_EINVAL, "sem_proj_set_gmres: NULL argument");
+    if (K < 0 || K > 64) fail(SEM_EINVAL, "sem_proj_set_gmres: K=%d outside [0,64]", K);
+    pr->gmres_K = K;
+  });
+}
+
 extern "C" int sem_proj_export(sem_proj pr, int i, double* p, double* Ap, void* stream) {
   return guarded([&] {
     if (!pr) fail(SEM_EINVAL, "sem_proj_export: NULL argument");
@@ -162,7 +171,8 @@ extern "C" int sem_pcg_solve_projected(sem_proj pr, sem_pmg pm, const double* b,
     } else {
       sem_solve_opts oi = o;
       oi.rtol = o.rtol / rel0;  // |r - A dx| <= rtol |b|
-      rc = sem_pcg_solve(pr->m, pm, r, dx, &oi, &inner, stream);
+      rc = pr->gmres_K > 0 ? sem_gmres_solve(pr->m, pm, pr->gmres_K, r, dx, &oi, &inner, stream)
+                           : sem_pcg_solve(pr->m, pm, r, dx, &oi, &inner, stream);
       inner.relres *= rel0;
       inner.relres_true *= rel0;
       solved = true;

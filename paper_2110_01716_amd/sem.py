@@ -104,6 +104,7 @@ _SIGS = {
     "sem_proj_destroy": (C.c_int, [_P]),
     "sem_proj_size": (C.c_int, [_P, C.POINTER(C.c_int)]),
     "sem_proj_reset": (C.c_int, [_P]),
+    "sem_proj_set_gmres": (C.c_int, [_P, C.c_int]),
     "sem_proj_export": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "sem_pcg_solve_projected": (C.c_int, [_P, _P, _P, _P, C.POINTER(sem_solve_opts), C.POINTER(sem_solve_info), _P]),
     "sem_status_string": (C.c_char_p, [C.c_int]),
@@ -400,6 +401,10 @@ def sem_proj_reset(h):
     _check(load().sem_proj_reset(h), "sem_proj_reset")
 
 
+def sem_proj_set_gmres(h, K: int):
+    _check(load().sem_proj_set_gmres(h, int(K)), "sem_proj_set_gmres")
+
+
 def sem_proj_export(h, i, p=None, Ap=None, stream=None):
     _check(load().sem_proj_export(h, i, _ptr(p), _ptr(Ap), _stream(stream)), "sem_proj_export")
 
@@ -478,10 +483,12 @@ class Pmg:
 class Projection:
     """Space of earlier solutions on one mesh (sem_proj_*)."""
 
-    def __init__(self, mesh: Mesh, L_max: int = 30):
+    def __init__(self, mesh: Mesh, L_max: int = 30, gmres_K: int = 0):
         self.mesh = mesh
         self.L_max = L_max
         self.h = sem_proj_create(mesh.h, L_max)
+        if gmres_K:
+            sem_proj_set_gmres(self.h, gmres_K)
 
     @property
     def size(self) -> int:

@@ -188,3 +188,28 @@ def test_projection_zero_rhs_and_errors(sem):
         sem.Projection(m, L_max=0)
     with pytest.raises(sem.SemError):
         pr.export(0, x)
+
+
+def test_projection_with_gmres_matches_oracle(sem):
+    import torch
+    print_case("proj-gmres")
+    bm = wl.box_mesh(3, 2, 3, N=5, deform=0.05, seed=36)
+    A, dot, _, dinv = _oracle(bm)
+    m = sem.Mesh.from_box(bm)
+    pr = sem.Projection(m, L_max=6, gmres_K=4)
+    sp = proj.ProjectionSpace(L_max=6)
+    k = 7
+
+    def inner(r, rtol):
+        return solvers.fgmres(A, lambda v: dinv * v, dot, r, K=4, fixed_iters=k).x
+
+    for step, b in enumerate(wl.rhs_sequence(bm, 4, modes=3, noise=1e-2, seed=12)):
+        x = torch.empty(bm.x.shape, dtype=torch.float64, device="cuda")
+        info = pr.solve(None, dev(b), x, sem.solve_opts(rtol=1e-14, fixed_iters=k))
+        xo, _, rel0 = proj.solve_projected(sp, A, dot, inner, b, rtol=1e-14)
+        assert info["status"] == 0 and info["iters"] == k and pr.size == sp.L
+        assert abs(info["relres_initial"] - rel0) <= 1e-9 * rel0
+        assert rel_err(host(x), xo) <= 1e-10
+    P, AP = _basis(sem, pr, bm)
+    for i in range(sp.L):
+        assert rel_err(P[i], sp.P[i]) <= 1e-9
