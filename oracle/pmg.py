@@ -6,7 +6,8 @@ The paper's pMG (Implementation, pMG paragraph): coarse-to-fine interpolation
 is the tensor contraction u_f = (Jhat x Jhat x Jhat) u_c with one 1D Jhat per
 level pair; smoothing by Chebyshev-accelerated point Jacobi; all pMG steps in
 32-bit (this oracle stays in FP64; the FP32 GPU path is compared against it
-with a tolerance). The coarsest level (N=1) is solved by Jacobi-PCG to a loose
+with a tolerance). The smoother is Chebyshev-accelerated point Jacobi or
+Chebyshev-accelerated overlapping Schwarz (oracle.schwarz). The coarsest level (N=1) is solved by Jacobi-PCG to a loose
 relative tolerance, standing in for the paper's CPU AMG coarse solve.
 
 Readings taken where the paper is silent:
@@ -31,6 +32,7 @@ from scipy.sparse.csgraph import connected_components
 from scipy.spatial import cKDTree
 
 from . import operators as ops
+from . import schwarz
 from . import solvers
 from .counter_rng import start_vector
 from .reference_ops import gll, interp_matrix, prolongation_1d
@@ -56,6 +58,13 @@ class Level:
 
     def dot(self, a, b):
         return float(np.sum(a * b / self.mult))
+
+    def M(self, v):
+        """The smoother's preconditioner: D^-1 (Jacobi) or the Schwarz operator."""
+        st = self.extra.get("schwarz")
+        if st is None:
+            return self.dinv * v
+        return schwarz.apply(st, v, self.extra["schwarz_variant"])
 
 
 def tensor_apply(M: np.ndarray, u: np.ndarray, n_in: int) -> np.ndarray:
@@ -110,8 +119,13 @@ def coarse_dirichlet(Nf, Nc, dir_f):
     return out.reshape(E, nc ** 3)
 
 
-def build_levels(N, x, y, z, gid, dirichlet, orders=None, rho=None, power_iters=20):
-    """Levels finest-first. rho: optional list of overrides (one per smoothed level)."""
+def build_levels(N, x, y, z, gid, dirichlet, orders=None, rho=None, power_iters=20, smoother="jacobi"):
+    """Levels finest-first. rho: optional list of overrides (one per smoothed level).
+
+    smoother: "jacobi" (Chebyshev-Jacobi), "asm" or "ras" (Chebyshev-accelerated
+    overlapping Schwarz with FDM local solves, see oracle.schwarz); rho is then
+    the largest eigenvalue estimate of M A for that M.
+    """
     if orders is None:
         orders = [N, (N - 1) // 2, 1] if N > 2 else [N, 1]
     assert orders[0] == N and orders[-1] == 1
@@ -133,11 +147,17 @@ def build_levels(N, x, y, z, gid, dirichlet, orders=None, rho=None, power_iters=
         lev.dinv = ops.jacobi_inverse(lev.N, lev.G, lev.gid, lev.dirichlet)
         levels.append(lev)
     for li, lev in enumerate(levels[:-1]):
+        if smoother != "jacobi":
+            lev.extra["schwarz"] = schwarz.setup(lev.N, lev.x, lev.y, lev.z, lev.gid, lev.dirichlet)
+            lev.extra["schwarz_variant"] = smoother
         if rho is not None and rho[li] is not None:
             lev.rho = float(rho[li])
         else:
             v0 = ops.mask(lev.dirichlet, start_vector(lev.gid))
-            lev.rho = solvers.power_rho(lev.A, lev.dinv, lev.dot, v0, iters=power_iters)
+            if smoother == "jacobi":
+                lev.rho = solvers.power_rho(lev.A, lev.dinv, lev.dot, v0, iters=power_iters)
+            else:
+                lev.rho = schwarz.power_rho(lev.A, lev.M, lev.dot, v0, iters=power_iters)
     return levels
 
 
@@ -188,13 +208,13 @@ def vcycle(levels, r, o: VCycleOpts, l: int = 0):
         return coarse_solve(lev, r, o)
     z = None
     for _ in range(o.pre):
-        z = solvers.chebyshev(lev.A, lev.dinv, r, lev.rho, o.degree, o.lo, o.hi, x0=z)
+        z = solvers.chebyshev(lev.A, lev.M, r, lev.rho, o.degree, o.lo, o.hi, x0=z)
     e = r - lev.A(z) if z is not None else r.copy()
     zc = vcycle(levels, restrict(levels, l, e), o, l + 1)
     zp = prolong(levels, l, zc)
     z = zp if z is None else z + zp
     for _ in range(o.post):
-        z = solvers.chebyshev(lev.A, lev.dinv, r, lev.rho, o.degree, o.lo, o.hi, x0=z)
+        z = solvers.chebyshev(lev.A, lev.M, r, lev.rho, o.degree, o.lo, o.hi, x0=z)
     return z
 
 

@@ -158,8 +158,16 @@ def fgmres(apply_A, apply_M, dot, b, K, rtol=1e-8, maxit=1000, fixed_iters=None)
     return SolveResult(x, it, relres, hist)
 
 
+def _precond(dinv, v):
+    return dinv(v) if callable(dinv) else dinv * v
+
+
 def chebyshev(apply_A, dinv, r, rho, degree, lo=0.1, hi=1.1, x0=None):
     """Degree-k Chebyshev-accelerated Jacobi on A x = r, eigen-interval [lo rho, hi rho].
+
+    dinv is the inverse diagonal D^-1 (an array), or any preconditioner given
+    as a callable v -> M v (the Chebyshev-accelerated Schwarz smoother), in
+    which case D^-1 below reads M.
 
     theta = (b+a)/2, delta = (b-a)/2, sigma = theta/delta, rho_0 = 1/sigma;
     res = r - A x0; d = D^-1 res / theta; x = x0 + d;
@@ -179,12 +187,12 @@ def chebyshev(apply_A, dinv, r, rho, degree, lo=0.1, hi=1.1, x0=None):
     else:
         res = r - apply_A(x0)
         x = x0.copy()
-    d = dinv * res / theta
+    d = _precond(dinv, res) / theta
     x = x + d
     for _ in range(degree - 1):
         res = res - apply_A(d)
         rho1 = 1.0 / (2.0 * sigma - rho0)
-        d = rho1 * rho0 * d + (2.0 * rho1 / delta) * (dinv * res)
+        d = rho1 * rho0 * d + (2.0 * rho1 / delta) * _precond(dinv, res)
         x = x + d
         rho0 = rho1
     return x
