@@ -172,10 +172,28 @@ typedef struct {
   int32_t coarse_maxit;       /* coarse iteration cap (500)                    */
   int32_t coarse_fixed_iters; /* > 0: exactly this many coarse iterations      */
   int32_t coarse_check_every; /* coarse convergence polled every k iters (8)   */
+  int32_t smoother;           /* SEM_SMOOTH_* (default Chebyshev-Jacobi)       */
 } sem_pmg_opts;
+
+/* pMG smoothers (Implementation, pMG paragraph): Chebyshev acceleration of
+ * point Jacobi, or of overlapping Schwarz with fast-diagonalization local
+ * solves on elements extended by one node layer across each face (eq. fdm),
+ * additive (ASM, counting weights) or restricted (RAS, own nodes only). */
+enum {
+  SEM_SMOOTH_CHEB_JACOBI = 0,
+  SEM_SMOOTH_CHEB_ASM = 1,
+  SEM_SMOOTH_CHEB_RAS = 2
+};
 
 /* Fills o with the defaults above (n_levels = 0 meaning the default schedule). */
 void sem_pmg_opts_default(sem_pmg_opts* o);
+
+/* Test hook: z = M r with the preconditioner the smoother accelerates at a
+ * smoothed level: D^-1 (Chebyshev-Jacobi) or W S, S = sum_e R_e^T A~_e^-1 R_e
+ * by fast diagonalization (eq. fdm) and W the ASM counting or RAS averaging
+ * weights (masked). r, z: device [E][Np] of that level in the smoother dtype,
+ * r consistent and masked. Synchronous. SEM_EINVAL on the coarsest level. */
+int sem_pmg_smoother_apply(sem_pmg p, int level, const void* r, void* z, void* stream);
 
 typedef struct {
   int32_t n_levels;

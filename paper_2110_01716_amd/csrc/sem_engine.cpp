@@ -92,6 +92,7 @@ struct Slot {
   double *r = nullptr, *z = nullptr, *p = nullptr, *w = nullptr;
   void *lr[kMaxLevels] = {}, *lx[kMaxLevels] = {}, *lres[kMaxLevels] = {}, *ld[kMaxLevels] = {},
        *lt[kMaxLevels] = {};
+  void *ls[kMaxLevels] = {}, *lovl[kMaxLevels] = {};  // Schwarz smoother: output and face overlaps
   double *cr = nullptr, *cx = nullptr, *cp = nullptr, *cw = nullptr;
   double* clocal = nullptr;  // restriction output on coarse element storage (assembled coarse level)
   double* dinv_h = nullptr;  // Jacobi-PCG: inverse diagonal of A + lambda B (Helmholtz solves)
@@ -141,6 +142,11 @@ size_t layout(Slot& s, uint8_t* base) {
       s.lres[l] = take(ts * nl);
       s.ld[l] = take(ts * nl);
       s.lt[l] = take(ts * nl);
+      if (s.pmg->lv[l].sw.on) {
+        const MeshData& m = s.level(l);
+        s.ls[l] = take(ts * nl);
+        s.lovl[l] = take(ts * 6 * (m.N + 1) * (m.N + 1) * m.E);
+      }
     }
     const MeshData& c = s.level(L - 1);
     const int64_t nc = c.assembled ? c.n_unique : c.nloc;
@@ -434,6 +440,57 @@ class Plan {
     }
   }
 
+  // out = QQ^T-summed, masked Schwarz sum of local FDM solves of in (weights applied by the caller)
+  template <typename T, typename FI, typename FO>
+  void schwarz(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, FI in_of, FO out_of, int skip_mode) {
+    std::map<int, std::vector<Slot*>> by;
+    for (Slot* s : S) by[s->level(l).N].push_back(s);
+    for (auto& kv : by) {
+      const int N = kv.first;
+      std::vector<SchwarzArgs<T>> args;
+      std::vector<SchwarzPullArgs<T>> pargs;
+      std::vector<int> starts{0};
+      bool ras = false;
+      for (Slot* s : kv.second) {
+        const MeshData& m = s->level(l);
+        const SchwarzData& sw = s->pmg->lv[l].sw;
+        ras = sw.ras;
+        SchwarzArgs<T> a;
+        a.E = m.E;
+        a.in = in_of(*s);
+        a.out = out_of(*s);
+        a.ovl = sw.ras ? nullptr : (T*)s->lovl[l];
+        a.desc = sw.desc.as<int>();
+        if constexpr (sizeof(T) == 8) {
+          a.S = sw.S64.as<double>();
+          a.lam = sw.L64.as<double>();
+        } else {
+          a.S = sw.S32.as<float>();
+          a.lam = sw.L32.as<float>();
+        }
+        a.skip = skip(*s, skip_mode);
+        args.push_back(a);
+        SchwarzPullArgs<T> p;
+        p.E = m.E;
+        p.out = a.out;
+        p.ovl = a.ovl;
+        p.desc = a.desc;
+        p.skip = a.skip;
+        pargs.push_back(p);
+        starts.push_back(starts.back() + schwarz_blocks(m.E));
+      }
+      const int64_t total = starts.back();
+      add(seq, args, starts, [N, total](const Table<SchwarzArgs<T>>& t, hipStream_t st) {
+        launch_schwarz<T>(N, 0, t, total, st);
+      });
+      if (!ras)  // one variant per group: the smoother is part of the plan signature
+        add(seq, pargs, starts, [N, total](const Table<SchwarzPullArgs<T>>& t, hipStream_t st) {
+          launch_schwarz_pull<T>(N, t, total, st);
+        });
+    }
+    gs<T>(seq, S, l, out_of, skip_mode);
+  }
+
   // skip modes: 0 none, 1 outer done, 2 outer or coarse done
   static Skip skip(const Slot& s, int mode) {
     Skip k;
@@ -473,8 +530,66 @@ void Plan::build_vcycle(Group& g) {
 
   auto Tp = [](void* p) { return (T*)p; };
 
+  // one Chebyshev-accelerated Schwarz sweep: D^-1 res of the Jacobi sweep
+  // becomes W S(res), computed into ls before each update
+  auto sweep_schwarz = [&](std::vector<Fn>& seq, int l, bool from_zero) {
+    const auto wts = [l](Slot& s) -> const T* {
+      if constexpr (sizeof(T) == 8) return s.pmg->lv[l].sw.w64.template as<double>();
+      else return s.pmg->lv[l].sw.w32.template as<float>();
+    };
+    const auto setv = [l, Tp, wts](Slot& s, VecArgs<T>& a) {
+      a.r = Tp(s.ls[l]);
+      a.x = Tp(s.lx[l]);
+      a.res = Tp(s.lres[l]);
+      a.d = Tp(s.ld[l]);
+      a.t = Tp(s.lt[l]);
+      a.dinv = wts(s);
+    };
+    const auto out_s = [l, Tp](Slot& s) { return Tp(s.ls[l]); };
+    if (from_zero) {
+      schwarz<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.lr[l]); }, out_s, SK);
+      vec<T>(seq, S, l, V_CHEB_INIT0, [l, setv](Slot& s, VecArgs<T>& a) {
+        setv(s, a);
+        a.c0 = 1.0 / s.pmg->lv[l].theta;
+      }, SK);
+    } else {
+      apply_A<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.lx[l]); }, [l, Tp](Slot& s) { return Tp(s.lt[l]); },
+                 false, SK);
+      vec<T>(seq, S, l, V_RES0, [l, Tp](Slot& s, VecArgs<T>& a) {
+        a.r = Tp(s.lr[l]);
+        a.res = Tp(s.lres[l]);
+        a.t = Tp(s.lt[l]);
+      }, SK);
+      schwarz<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.lres[l]); }, out_s, SK);
+      vec<T>(seq, S, l, V_CHEB_UPD0, [l, setv](Slot& s, VecArgs<T>& a) {
+        setv(s, a);
+        a.c2 = 1.0 / s.pmg->lv[l].theta;
+      }, SK);
+    }
+    for (int j = 1; j < K; ++j) {
+      apply_A<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.ld[l]); }, [l, Tp](Slot& s) { return Tp(s.lt[l]); },
+                 false, SK);
+      const VecOp rop = (from_zero && j == 1) ? V_RES0 : V_RES;
+      vec<T>(seq, S, l, rop, [l, Tp](Slot& s, VecArgs<T>& a) {
+        a.r = Tp(s.lr[l]);
+        a.res = Tp(s.lres[l]);
+        a.t = Tp(s.lt[l]);
+      }, SK);
+      schwarz<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.lres[l]); }, out_s, SK);
+      vec<T>(seq, S, l, V_CHEB_UPD, [l, j, setv](Slot& s, VecArgs<T>& a) {
+        setv(s, a);
+        a.c1 = s.pmg->lv[l].c1[j - 1];
+        a.c2 = s.pmg->lv[l].c2[j - 1];
+      }, SK);
+    }
+  };
+
   // one Chebyshev sweep at level l; from_zero: x0 = 0
   auto sweep = [&](std::vector<Fn>& seq, int l, bool from_zero) {
+    if (S[0]->pmg->lv[l].sw.on) {
+      sweep_schwarz(seq, l, from_zero);
+      return;
+    }
     const auto setv = [l, Tp](Slot& s, VecArgs<T>& a) {
       a.r = Tp(s.lr[l]);
       a.x = Tp(s.lx[l]);
@@ -703,8 +818,9 @@ static std::string signature(const Slot& s) {
   if (!s.pmg) return s.lam() != 0.0 ? "jacobi-helmholtz" : "jacobi";
   const sem_pmg_opts& o = s.pmg->o;
   char buf[128];
-  snprintf(buf, sizeof(buf), "pmg L%d t%d k%d pre%d post%d cf%d cm%d cc%d", s.pmg->n_levels, (int)o.smoother_dtype,
-           o.cheb_degree, o.pre, o.post, o.coarse_fixed_iters, o.coarse_maxit, o.coarse_check_every);
+  snprintf(buf, sizeof(buf), "pmg L%d t%d k%d pre%d post%d cf%d cm%d cc%d sm%d", s.pmg->n_levels,
+           (int)o.smoother_dtype, o.cheb_degree, o.pre, o.post, o.coarse_fixed_iters, o.coarse_maxit,
+           o.coarse_check_every, o.smoother);
   return buf;
 }
 

@@ -177,7 +177,12 @@ enum VecOp : int {
   V_CHEB_INITX,       // res = r - t; d = dinv res / theta; x += d
   V_CHEB_STEP,        // res -= t; d = c1 d + c2 dinv res; x += d
   V_CHEB_STEP0,       // first step after INIT0: res = r - t; d = c1 d + c2 dinv res; x += d
+  V_RES0,             // res = r - t
+  V_RES,              // res -= t
+  V_CHEB_UPD,         // d = c1 d + c2 dinv r; x += d   (r: a smoother's preconditioned residual)
+  V_CHEB_UPD0,        // d = c2 dinv r; x += d
   V_ZERO,             // x = 0
+  V_FILL,             // x = c0
   V_COPY,             // x = r
   V_SCALE_DINV,       // x = dinv * r
   V_NORMALIZE,        // x = r * scal[S_TMP]
@@ -292,6 +297,48 @@ struct UsumArgs {
   Skip skip;
 };
 
+// Overlapping Schwarz smoother, one block per element (N+3)^3 extended box.
+// desc [E][6][8] int32 per face: {nbr, g_off, g_su, g_sv, p_off, p_su, p_sv, kind}:
+//   the extension value for face node (u, v) is in[nbr*Np + g_off + u*g_su + v*g_sv];
+//   the element's depth-1 node (u, v) behind the face receives
+//   ovl[nbr*6*NP^2 + p_off + u*p_su + v*p_sv]; kind 0 neighbour, 1 Dirichlet, 2 Neumann.
+// S [E][3][NE][NE] (row: ext index, column: mode), lam [E][3][NE].
+// mode 0: fast-diagonalization solve; mode 1: identity on the active positions
+// (the counting function). out: own (N+1)^3 block; ovl [E][6][NP^2] (face
+// layers of the local solution, v*NP + u), skipped when null (RAS).
+template <typename T>
+struct SchwarzArgs {
+  int64_t E = 0;
+  const T* in = nullptr;
+  T* out = nullptr;
+  T* ovl = nullptr;
+  const int* desc = nullptr;
+  const T* S = nullptr;
+  const T* lam = nullptr;
+  Skip skip;
+};
+// out[e][depth-1 node behind face f] += pulled overlap of the neighbour across f
+template <typename T>
+struct SchwarzPullArgs {
+  int64_t E = 0;
+  T* out = nullptr;
+  const T* ovl = nullptr;
+  const int* desc = nullptr;
+  Skip skip;
+};
+// per element: 8 corner global IDs (lexicographic i, j, k), 6 face flags
+// (1 = every node of the face is Dirichlet), 3 mean lengths (r, s, t)
+struct SchwarzInfoArgs {
+  int N = 0;
+  int64_t E = 0;
+  const double *x = nullptr, *y = nullptr, *z = nullptr;
+  const int64_t* gid = nullptr;
+  const uint8_t* dmask = nullptr;
+  int64_t* corners = nullptr;
+  uint8_t* face_dir = nullptr;
+  double* lengths = nullptr;
+};
+
 // multi-dot: partial[k][blk] = sum over owned points of v[k] . y (k < K)
 struct MdotArgs {
   int64_t n = 0;
@@ -337,6 +384,12 @@ int64_t spmv_blocks(int64_t n);
 void launch_mdot(const MdotArgs& a, hipStream_t s);            // grid: vec_blocks(n) x ceil(K/8)
 void launch_mfin(const double* partial, int64_t stride, int64_t nblk, int K, double* out, hipStream_t s);
 void launch_lincomb(const LincombArgs& a, hipStream_t s);
+int schwarz_blocks(int64_t E);  // one block per element
+template <typename T>
+void launch_schwarz(int N, int mode, const Table<SchwarzArgs<T>>& t, int64_t total_blocks, hipStream_t s);
+template <typename T>
+void launch_schwarz_pull(int N, const Table<SchwarzPullArgs<T>>& t, int64_t total_blocks, hipStream_t s);
+void launch_schwarz_info(const SchwarzInfoArgs& a, hipStream_t s);
 void launch_spmv(const Table<SpmvArgs>& t, int64_t total_blocks, hipStream_t s);
 void launch_usum(const Table<UsumArgs>& t, int64_t total_blocks, hipStream_t s);
 template <typename Tf, typename Tc>
@@ -373,6 +426,8 @@ void apply_A(const MeshData& m, sem_dtype t, const void* u, void* Au, hipStream_
 void apply_H(const MeshData& m, double lambda, const double* u, double* Hu, hipStream_t s);
 // inverse Jacobi diagonal of M QQ^T (A_L + lambda B) into out (FP64), using tmp [nloc]
 void helmholtz_dinv(const MeshData& m, double lambda, double* out, double* tmp, hipStream_t s);
+// QQ^T (and the Dirichlet mask if mask != 0) in place, FP64 or FP32
+void mesh_gs(const MeshData& m, sem_dtype t, void* v, int mask, hipStream_t s);
 // FP64 unique-DOF inner product with caller scratch partial [2 * vec_blocks(nloc)]
 double mesh_dot_ws(const MeshData& m, const double* a, const double* b, double* partial, hipStream_t s);
 // out[k] = (v_k, y) over unique DOFs for k < K; v is a device array of K
@@ -403,13 +458,28 @@ void vcycle_runner_destroy(VcycleRunner* v);
 // p-multigrid hierarchy
 // ---------------------------------------------------------------------------
 namespace sem {
+// overlapping Schwarz data of one smoothed level (layouts as in SchwarzArgs)
+struct SchwarzData {
+  bool on = false;
+  bool ras = false;
+  DevBuf desc;                   // int32 [E][6][8]
+  DevBuf S64, L64, S32, L32;     // FDM eigenvectors / eigenvalues
+  DevBuf w64, w32;               // weights: 1 / counting function (ASM) or 1 / multiplicity (RAS)
+};
+
 struct PmgLevel {
   sem_mesh_s* mesh = nullptr;    // level mesh (level 0: the user's mesh)
   double rho = 0, theta = 0, delta = 0;
   std::vector<double> c1, c2;    // Chebyshev step coefficients, steps 1..k-1
   DevBuf J;                      // prolongation from level l+1: (N_l+1) x (N_{l+1}+1)
   DevBuf JT;                     // restriction to level l+1:   (N_{l+1}+1) x (N_l+1)
+  SchwarzData sw;
 };
+// builds the Schwarz data of a level (sem_schwarz.cpp)
+void schwarz_setup(const MeshData& m, bool ras, SchwarzData& sw, hipStream_t s);
+// z = W S(r) in FP64 or FP32 (the smoother's preconditioner); tmp_ovl [E][6][NP^2] of the same type
+void schwarz_apply(const MeshData& m, const SchwarzData& sw, sem_dtype t, const void* r, void* z, void* tmp_ovl,
+                   hipStream_t s);
 void chebyshev_coefficients(PmgLevel& lv, double lo, double hi, int degree);
 }  // namespace sem
 

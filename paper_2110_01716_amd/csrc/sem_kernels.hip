@@ -444,8 +444,22 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
       const T d = c1 * Dd[l] + c2 * DINV[l] * res;
       Dd[l] = d;
       X[l] += d;
+    } else if constexpr (OP == V_RES0) {
+      RES[l] = R[l] - Tt[l];
+    } else if constexpr (OP == V_RES) {
+      RES[l] = RES[l] - Tt[l];
+    } else if constexpr (OP == V_CHEB_UPD) {
+      const T d = c1 * Dd[l] + c2 * DINV[l] * R[l];
+      Dd[l] = d;
+      X[l] += d;
+    } else if constexpr (OP == V_CHEB_UPD0) {
+      const T d = c2 * DINV[l] * R[l];
+      Dd[l] = d;
+      X[l] += d;
     } else if constexpr (OP == V_ZERO) {
       X[l] = T(0);
+    } else if constexpr (OP == V_FILL) {
+      X[l] = c0;
     } else if constexpr (OP == V_COPY) {
       X[l] = R[l];
     } else if constexpr (OP == V_SCALE_DINV) {
@@ -493,6 +507,7 @@ void launch_vec(VecOp op, const Table<VecArgs<T>>& t, int64_t total_blocks, hipS
     SEM_VEC_CASE(V_CHEB_STEP) SEM_VEC_CASE(V_ZERO) SEM_VEC_CASE(V_COPY)
     SEM_VEC_CASE(V_SCALE_DINV) SEM_VEC_CASE(V_NORMALIZE) SEM_VEC_CASE(V_TRUE_RES)
     SEM_VEC_CASE(V_DIV_DINV) SEM_VEC_CASE(V_SCALE) SEM_VEC_CASE(V_AXPY)
+    SEM_VEC_CASE(V_RES0) SEM_VEC_CASE(V_RES) SEM_VEC_CASE(V_CHEB_UPD) SEM_VEC_CASE(V_CHEB_UPD0) SEM_VEC_CASE(V_FILL)
 #undef SEM_VEC_CASE
     default:
       fail(SEM_EINVAL, "unknown vector op %d", (int)op);
@@ -939,6 +954,292 @@ __global__ __launch_bounds__(kVecThreads) void k_lincomb(LincombArgs a) {
 void launch_lincomb(const LincombArgs& a, hipStream_t s) {
   if (a.n <= 0) return;
   hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((a.n + kVecThreads - 1) / kVecThreads)), dim3(kVecThreads), 0, s, a);
+  SEM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// overlapping Schwarz smoother with fast-diagonalization local solves
+// (Implementation, pMG smoothers, eq. fdm)
+// ---------------------------------------------------------------------------
+// One workgroup per element. Thread (a, b) of the (N+3)^2 grid owns the
+// column c = 0..N+2 of the extended box: the t-direction transforms run in
+// registers, the r and s transforms read the box staged in LDS (as in k_ax).
+template <int N>
+struct SchCfg {
+  static constexpr int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
+  static constexpr int NE = N + 3, NE2 = NE * NE, NE3 = NE2 * NE;
+  static constexpr int THREADS = ((NE2 + 63) / 64) * 64;
+};
+
+int schwarz_blocks(int64_t E) { return (int)E; }
+
+template <int N, typename T, int MODE>
+__global__ __launch_bounds__(SchCfg<N>::THREADS) void k_schwarz(Table<SchwarzArgs<T>> tab) {
+  using C = SchCfg<N>;
+  constexpr int NP = C::NP, NP2 = C::NP2, NP3 = C::NP3, NE = C::NE, NE2 = C::NE2;
+  __shared__ T sS[3][NE2];
+  __shared__ T sL[3][NE];
+  __shared__ T box[C::NE3];  // [c][b][a]
+  __shared__ int sd[6][8];
+  int lb;
+  const SchwarzArgs<T> a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  const int64_t e = lb;
+  const int tid = threadIdx.x;
+  if (tid < 48) sd[tid >> 3][tid & 7] = gl(a.desc)[e * 48 + tid];
+  if constexpr (MODE == 0) {
+    const SEM_GLOBAL T* Sg = gl(a.S) + e * 3 * NE2;
+    for (int k = tid; k < 3 * NE2; k += C::THREADS) sS[k / NE2][k % NE2] = Sg[k];
+    const SEM_GLOBAL T* Lg = gl(a.lam) + e * 3 * NE;
+    for (int k = tid; k < 3 * NE; k += C::THREADS) sL[k / NE][k % NE] = Lg[k];
+  }
+  __syncthreads();
+  const int ia = tid % NE, ib = tid / NE;
+  const bool live = ib < NE;
+  const bool ca = ia >= 1 && ia <= N + 1, cb = ib >= 1 && ib <= N + 1;
+  const SEM_GLOBAL T* in = gl(a.in);
+  auto face = [&](int f, int u, int v) -> T {
+    const int nb = sd[f][0];
+    if (nb < 0) return T(0);
+    return in[(int64_t)nb * NP3 + sd[f][1] + u * sd[f][2] + v * sd[f][3]];
+  };
+  T x[NE];
+#pragma unroll
+  for (int c = 0; c < NE; ++c) x[c] = T(0);
+  if (live) {
+    if (ca && cb) {
+      const SEM_GLOBAL T* ue = in + e * NP3 + (ib - 1) * NP + (ia - 1);
+#pragma unroll
+      for (int c = 1; c <= N + 1; ++c) x[c] = ue[(c - 1) * NP2];
+      x[0] = face(4, ia - 1, ib - 1);
+      x[N + 2] = face(5, ia - 1, ib - 1);
+    } else if (!ca && cb) {
+      const int f = ia == 0 ? 0 : 1;
+#pragma unroll
+      for (int c = 1; c <= N + 1; ++c) x[c] = face(f, ib - 1, c - 1);
+    } else if (ca && !cb) {
+      const int f = ib == 0 ? 2 : 3;
+#pragma unroll
+      for (int c = 1; c <= N + 1; ++c) x[c] = face(f, ia - 1, c - 1);
+    }
+  }
+  T o[NE];
+  if constexpr (MODE == 1) {
+    // identity on the active positions of the subdomain (edge columns hold zeros)
+    auto lo = [](int k) { return k == 0 ? 0 : k == 1 ? 2 : 1; };
+    auto hi = [](int k) { return k == 0 ? N + 2 : k == 1 ? N : N + 1; };
+    const bool in_ab = ia >= lo(sd[0][7]) && ia <= hi(sd[1][7]) && ib >= lo(sd[2][7]) && ib <= hi(sd[3][7]);
+#pragma unroll
+    for (int c = 0; c < NE; ++c) o[c] = (in_ab && c >= lo(sd[4][7]) && c <= hi(sd[5][7])) ? x[c] : T(0);
+  } else {
+    // forward: S_t^T in registers
+    T y[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+      T acc = 0;
+#pragma unroll
+      for (int c = 0; c < NE; ++c) acc += sS[2][c * NE + m] * x[c];
+      y[m] = acc;
+    }
+    if (live)
+#pragma unroll
+      for (int c = 0; c < NE; ++c) box[c * NE2 + ib * NE + ia] = y[c];
+    __syncthreads();
+    // S_r^T along a
+    if (live)
+#pragma unroll
+      for (int c = 0; c < NE; ++c) {
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) acc += sS[0][q * NE + ia] * box[c * NE2 + ib * NE + q];
+        y[c] = acc;
+      }
+    __syncthreads();
+    if (live)
+#pragma unroll
+      for (int c = 0; c < NE; ++c) box[c * NE2 + ib * NE + ia] = y[c];
+    __syncthreads();
+    // S_s^T along b, then divide by the eigenvalue sums
+    if (live)
+#pragma unroll
+      for (int c = 0; c < NE; ++c) {
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) acc += sS[1][q * NE + ib] * box[c * NE2 + q * NE + ia];
+        const T lam = sL[0][ia] + sL[1][ib] + sL[2][c];
+        y[c] = lam > T(0) ? acc / lam : T(0);
+      }
+    __syncthreads();
+    if (live)
+#pragma unroll
+      for (int c = 0; c < NE; ++c) box[c * NE2 + ib * NE + ia] = y[c];
+    __syncthreads();
+    // backward: S_s along b
+    if (live)
+#pragma unroll
+      for (int c = 0; c < NE; ++c) {
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) acc += sS[1][ib * NE + q] * box[c * NE2 + q * NE + ia];
+        y[c] = acc;
+      }
+    __syncthreads();
+    if (live)
+#pragma unroll
+      for (int c = 0; c < NE; ++c) box[c * NE2 + ib * NE + ia] = y[c];
+    __syncthreads();
+    // S_r along a
+    if (live)
+#pragma unroll
+      for (int c = 0; c < NE; ++c) {
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) acc += sS[0][ia * NE + q] * box[c * NE2 + ib * NE + q];
+        y[c] = acc;
+      }
+    // S_t in registers
+#pragma unroll
+    for (int c = 0; c < NE; ++c) {
+      T acc = 0;
+#pragma unroll
+      for (int m = 0; m < NE; ++m) acc += sS[2][c * NE + m] * y[m];
+      o[c] = acc;
+    }
+  }
+  if (!live) return;
+  SEM_GLOBAL T* ovl = a.ovl ? gl(a.ovl) + e * 6 * NP2 : nullptr;
+  if (ca && cb) {
+    SEM_GLOBAL T* oe = gl(a.out) + e * NP3 + (ib - 1) * NP + (ia - 1);
+#pragma unroll
+    for (int c = 1; c <= N + 1; ++c) oe[(c - 1) * NP2] = o[c];
+    if (ovl) {
+      ovl[4 * NP2 + (ib - 1) * NP + (ia - 1)] = o[0];
+      ovl[5 * NP2 + (ib - 1) * NP + (ia - 1)] = o[N + 2];
+    }
+  } else if (ovl && !ca && cb) {
+    const int f = ia == 0 ? 0 : 1;
+#pragma unroll
+    for (int c = 1; c <= N + 1; ++c) ovl[f * NP2 + (c - 1) * NP + (ib - 1)] = o[c];
+  } else if (ovl && ca && !cb) {
+    const int f = ib == 0 ? 2 : 3;
+#pragma unroll
+    for (int c = 1; c <= N + 1; ++c) ovl[f * NP2 + (c - 1) * NP + (ia - 1)] = o[c];
+  }
+}
+
+constexpr int kPullThreads = 256;
+
+template <int N, typename T>
+__global__ __launch_bounds__(kPullThreads) void k_schwarz_pull(Table<SchwarzPullArgs<T>> tab) {
+  constexpr int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
+  __shared__ int sd[6][8];
+  int lb;
+  const SchwarzPullArgs<T> a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  const int64_t e = lb;
+  if (threadIdx.x < 48) sd[threadIdx.x >> 3][threadIdx.x & 7] = gl(a.desc)[e * 48 + threadIdx.x];
+  __syncthreads();
+  const SEM_GLOBAL T* ovl = gl(a.ovl);
+  auto pull = [&](int f, int u, int v) -> T {
+    const int nb = sd[f][0];
+    if (nb < 0) return T(0);
+    return ovl[(int64_t)nb * 6 * NP2 + sd[f][4] + u * sd[f][5] + v * sd[f][6]];
+  };
+  SEM_GLOBAL T* out = gl(a.out) + e * NP3;
+  for (int p = threadIdx.x; p < NP3; p += kPullThreads) {
+    const int i = p % NP, j = (p / NP) % NP, k = p / NP2;
+    const bool any = i == 1 || i == N - 1 || j == 1 || j == N - 1 || k == 1 || k == N - 1;
+    if (!any) continue;
+    T acc = 0;
+    if (i == 1) acc += pull(0, j, k);
+    if (i == N - 1) acc += pull(1, j, k);
+    if (j == 1) acc += pull(2, i, k);
+    if (j == N - 1) acc += pull(3, i, k);
+    if (k == 1) acc += pull(4, i, j);
+    if (k == N - 1) acc += pull(5, i, j);
+    out[p] += acc;
+  }
+}
+
+template <typename T>
+void launch_schwarz(int N, int mode, const Table<SchwarzArgs<T>>& t, int64_t total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  const dim3 g((unsigned)total_blocks);
+  switch (N) {
+#define SEM_SCH_CASE(n)                                                                                     case n:                                                                                                     if (mode == 0) hipLaunchKernelGGL((k_schwarz<n, T, 0>), g, dim3(SchCfg<n>::THREADS), 0, s, t);            else hipLaunchKernelGGL((k_schwarz<n, T, 1>), g, dim3(SchCfg<n>::THREADS), 0, s, t);                      break;
+    SEM_SCH_CASE(2) SEM_SCH_CASE(3) SEM_SCH_CASE(4) SEM_SCH_CASE(5) SEM_SCH_CASE(6) SEM_SCH_CASE(7)
+    SEM_SCH_CASE(8) SEM_SCH_CASE(9) SEM_SCH_CASE(10) SEM_SCH_CASE(11) SEM_SCH_CASE(12) SEM_SCH_CASE(13)
+    SEM_SCH_CASE(14) SEM_SCH_CASE(15)
+#undef SEM_SCH_CASE
+    default:
+      fail(SEM_EINVAL, "Schwarz smoother: unsupported order N=%d", N);
+  }
+  SEM_HIP(hipGetLastError());
+}
+template void launch_schwarz<double>(int, int, const Table<SchwarzArgs<double>>&, int64_t, hipStream_t);
+template void launch_schwarz<float>(int, int, const Table<SchwarzArgs<float>>&, int64_t, hipStream_t);
+
+template <typename T>
+void launch_schwarz_pull(int N, const Table<SchwarzPullArgs<T>>& t, int64_t total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  const dim3 g((unsigned)total_blocks), b(kPullThreads);
+  switch (N) {
+#define SEM_PULL_CASE(n) case n: hipLaunchKernelGGL((k_schwarz_pull<n, T>), g, b, 0, s, t); break;
+    SEM_PULL_CASE(2) SEM_PULL_CASE(3) SEM_PULL_CASE(4) SEM_PULL_CASE(5) SEM_PULL_CASE(6) SEM_PULL_CASE(7)
+    SEM_PULL_CASE(8) SEM_PULL_CASE(9) SEM_PULL_CASE(10) SEM_PULL_CASE(11) SEM_PULL_CASE(12) SEM_PULL_CASE(13)
+    SEM_PULL_CASE(14) SEM_PULL_CASE(15)
+#undef SEM_PULL_CASE
+    default:
+      fail(SEM_EINVAL, "Schwarz smoother: unsupported order N=%d", N);
+  }
+  SEM_HIP(hipGetLastError());
+}
+template void launch_schwarz_pull<double>(int, const Table<SchwarzPullArgs<double>>&, int64_t, hipStream_t);
+template void launch_schwarz_pull<float>(int, const Table<SchwarzPullArgs<float>>&, int64_t, hipStream_t);
+
+// per element: corner IDs, all-Dirichlet face flags, mean lengths (one thread per element)
+__global__ __launch_bounds__(64) void k_schwarz_info(SchwarzInfoArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (e >= a.E) return;
+  const int N = a.N, NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
+  const int64_t b = e * NP3;
+  const SEM_GLOBAL int64_t* gid = gl(a.gid);
+  const SEM_GLOBAL uint8_t* dm = gl(a.dmask);
+  const SEM_GLOBAL double* X = gl(a.x);
+  const SEM_GLOBAL double* Y = gl(a.y);
+  const SEM_GLOBAL double* Z = gl(a.z);
+  for (int q = 0; q < 8; ++q) {
+    const int i = (q & 1) ? N : 0, j = (q & 2) ? N : 0, k = (q & 4) ? N : 0;
+    gl(a.corners)[e * 8 + q] = gid[b + i + NP * j + NP2 * k];
+  }
+  for (int f = 0; f < 6; ++f) {
+    const int axis = f >> 1, d = (f & 1) ? N : 0;
+    int all = 1;
+    for (int u = 0; u < NP; ++u)
+      for (int v = 0; v < NP; ++v) {
+        const int p = axis == 0 ? d + NP * u + NP2 * v : axis == 1 ? u + NP * d + NP2 * v : u + NP * v + NP2 * d;
+        all &= dm[b + p] != 0;
+      }
+    gl(a.face_dir)[e * 6 + f] = (uint8_t)all;
+  }
+  for (int axis = 0; axis < 3; ++axis) {
+    double sum = 0.0;
+    for (int u = 0; u < NP; ++u)
+      for (int v = 0; v < NP; ++v) {
+        int p0, p1;
+        if (axis == 0) { p0 = NP * u + NP2 * v; p1 = p0 + N; }
+        else if (axis == 1) { p0 = u + NP2 * v; p1 = p0 + N * NP; }
+        else { p0 = u + NP * v; p1 = p0 + N * NP2; }
+        const double dx = X[b + p1] - X[b + p0], dy = Y[b + p1] - Y[b + p0], dz = Z[b + p1] - Z[b + p0];
+        sum += sqrt(dx * dx + dy * dy + dz * dz);
+      }
+    gl(a.lengths)[e * 3 + axis] = sum / NP2;
+  }
+}
+
+void launch_schwarz_info(const SchwarzInfoArgs& a, hipStream_t s) {
+  if (a.E <= 0) return;
+  hipLaunchKernelGGL(k_schwarz_info, dim3((unsigned)((a.E + 63) / 64)), dim3(64), 0, s, a);
   SEM_HIP(hipGetLastError());
 }
 

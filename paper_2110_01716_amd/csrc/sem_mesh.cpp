@@ -105,6 +105,11 @@ static void gs_apply(const MeshData& m, T* v, int mask, hipStream_t s) {
   launch_gs<T>(t, gs_blocks(m.n_shared, t.one.n_dir), s);
 }
 
+void mesh_gs(const MeshData& m, sem_dtype t, void* v, int mask, hipStream_t s) {
+  if (t == SEM_F64) gs_apply<double>(m, (double*)v, mask, s);
+  else gs_apply<float>(m, (float*)v, mask, s);
+}
+
 void apply_A(const MeshData& m, sem_dtype t, const void* u, void* Au, hipStream_t s) {
   if (t == SEM_F64) {
     ax_range<double>(m, (const double*)u, (double*)Au, 0, m.E, nullptr, 0.0, nullptr, s);

@@ -160,6 +160,26 @@ double power_rho(const MeshData& m, int iters, hipStream_t s) {
   return num / den;
 }
 
+// rho of W S A (Schwarz smoother): |M A v| after normalised power iterations
+double power_rho_schwarz(const MeshData& m, const SchwarzData& sw, int iters, hipStream_t s) {
+  DevBuf v, w, ovl;
+  v.alloc(sizeof(double) * m.nloc);
+  w.alloc(sizeof(double) * m.nloc);
+  ovl.alloc(sizeof(double) * 6 * (m.N + 1) * (m.N + 1) * m.E);
+  launch_start_vector(m.nloc, m.gid.as<int64_t>(), m.dmask.as<uint8_t>(), v.as<double>(), s);
+  double nrm = std::sqrt(mesh_dot(m, SEM_F64, v.p, v.p, s));
+  if (!(nrm > 0)) return 1.0;
+  vec1(m, V_SCALE, v.as<double>(), v.as<double>(), 1.0 / nrm, s);
+  for (int it = 0; it <= iters; ++it) {
+    apply_A(m, SEM_F64, v.p, w.p, s);
+    schwarz_apply(m, sw, SEM_F64, w.p, v.p, ovl.p, s);
+    nrm = std::sqrt(mesh_dot(m, SEM_F64, v.p, v.p, s));
+    if (it == iters) break;
+    vec1(m, V_SCALE, v.as<double>(), v.as<double>(), 1.0 / nrm, s);
+  }
+  return nrm;
+}
+
 void upload_matrix(DevBuf& dst, const std::vector<double>& h, hipStream_t s) {
   dst.alloc(sizeof(double) * h.size());
   SEM_HIP(hipMemcpyAsync(dst.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
@@ -186,6 +206,7 @@ extern "C" void sem_pmg_opts_default(sem_pmg_opts* o) {
   o->coarse_maxit = 500;
   o->coarse_fixed_iters = 0;
   o->coarse_check_every = 8;
+  o->smoother = SEM_SMOOTH_CHEB_JACOBI;
 }
 
 extern "C" int sem_pmg_setup(sem_mesh mh, const sem_pmg_opts* oin, sem_pmg* out) {
@@ -224,6 +245,8 @@ extern "C" int sem_pmg_setup(sem_mesh mh, const sem_pmg_opts* oin, sem_pmg* out)
     if (o.pre < 0 || o.post < 0 || o.pre + o.post < 1) fail(SEM_EINVAL, "sem_pmg_setup: need pre + post >= 1");
     if (!(o.eig_hi > o.eig_lo) || !(o.eig_lo > 0)) fail(SEM_EINVAL, "sem_pmg_setup: need 0 < eig_lo < eig_hi");
     if (o.coarse_maxit < 1) fail(SEM_EINVAL, "sem_pmg_setup: coarse_maxit < 1");
+    if (o.smoother < SEM_SMOOTH_CHEB_JACOBI || o.smoother > SEM_SMOOTH_CHEB_RAS)
+      fail(SEM_EINVAL, "sem_pmg_setup: unknown smoother %d", o.smoother);
     if (o.coarse_check_every < 1) P->o.coarse_check_every = 8;
     // every transfer pair must have a kernel
     for (int l = 0; l + 1 < P->n_levels; ++l) (void)xfer_blocks(P->orders[l], P->orders[l + 1], 1);
@@ -273,7 +296,9 @@ extern "C" int sem_pmg_setup(sem_mesh mh, const sem_pmg_opts* oin, sem_pmg* out)
     }
     for (int l = 0; l + 1 < P->n_levels; ++l) {
       PmgLevel& lv = P->lv[l];
+      if (o.smoother != SEM_SMOOTH_CHEB_JACOBI) schwarz_setup(lv.mesh->d, o.smoother == SEM_SMOOTH_CHEB_RAS, lv.sw, s);
       if (o.rho_override) lv.rho = o.rho_override[l];
+      else if (lv.sw.on) lv.rho = power_rho_schwarz(lv.mesh->d, lv.sw, o.power_iters, s);
       else lv.rho = power_rho(lv.mesh->d, o.power_iters, s);
       if (!(lv.rho > 0) || !std::isfinite(lv.rho)) fail(SEM_EINVAL, "sem_pmg_setup: invalid rho %g at level %d", lv.rho, l);
       chebyshev_coefficients(lv, o.eig_lo, o.eig_hi, o.cheb_degree);
@@ -299,6 +324,9 @@ extern "C" int sem_pmg_query(sem_pmg p, sem_pmg_info* info) {
       info->n_unique[l] = p->lv[l].mesh->d.n_unique;
       if (l > 0) bytes += p->lv[l].mesh->d.resident_bytes();
       bytes += (int64_t)(p->lv[l].J.bytes + p->lv[l].JT.bytes);
+      const SchwarzData& sw = p->lv[l].sw;
+      bytes += (int64_t)(sw.desc.bytes + sw.S64.bytes + sw.L64.bytes + sw.S32.bytes + sw.L32.bytes + sw.w64.bytes +
+                         sw.w32.bytes);
     }
     info->resident_bytes = bytes;
   });
@@ -309,5 +337,32 @@ extern "C" int sem_pmg_level(sem_pmg p, int level, sem_mesh* out) {
     if (!p || !out) fail(SEM_EINVAL, "sem_pmg_level: NULL argument");
     if (level < 0 || level >= p->n_levels) fail(SEM_EINVAL, "sem_pmg_level: level %d outside [0,%d)", level, p->n_levels);
     *out = p->lv[level].mesh;
+  });
+}
+
+extern "C" int sem_pmg_smoother_apply(sem_pmg p, int level, const void* r, void* z, void* stream) {
+  return guarded([&] {
+    if (!p || !r || !z) fail(SEM_EINVAL, "sem_pmg_smoother_apply: NULL argument");
+    if (level < 0 || level + 1 >= p->n_levels)
+      fail(SEM_EINVAL, "sem_pmg_smoother_apply: level %d is not a smoothed level", level);
+    hipStream_t s = (hipStream_t)stream;
+    const PmgLevel& lv = p->lv[level];
+    const MeshData& m = lv.mesh->d;
+    const sem_dtype t = p->o.smoother_dtype;
+    if (lv.sw.on) {
+      DevBuf ovl;
+      ovl.alloc((t == SEM_F64 ? 8 : 4) * (size_t)6 * (m.N + 1) * (m.N + 1) * m.E);
+      schwarz_apply(m, lv.sw, t, r, z, ovl.p, s);
+      SEM_HIP(hipStreamSynchronize(s));
+    } else if (t == SEM_F64) {
+      vec_op1(V_SCALE_DINV, m.nloc, (double*)z, (const double*)r, 0.0, m.dinv64.as<double>(), s);
+    } else {
+      Table<VecArgs<float>> tv;
+      tv.one.n = m.nloc;
+      tv.one.x = (float*)z;
+      tv.one.r = (float*)const_cast<void*>(r);
+      tv.one.dinv = m.dinv32.as<float>();
+      launch_vec<float>(V_SCALE_DINV, tv, vec_blocks(m.nloc), s);
+    }
   });
 }

@@ -45,7 +45,11 @@ class sem_pmg_opts(C.Structure):
                 ("cheb_degree", C.c_int32), ("pre", C.c_int32), ("post", C.c_int32), ("eig_lo", C.c_double),
                 ("eig_hi", C.c_double), ("power_iters", C.c_int32), ("rho_override", C.c_void_p),
                 ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int32), ("coarse_fixed_iters", C.c_int32),
-                ("coarse_check_every", C.c_int32)]
+                ("coarse_check_every", C.c_int32), ("smoother", C.c_int32)]
+
+
+SEM_SMOOTH_CHEB_JACOBI, SEM_SMOOTH_CHEB_ASM, SEM_SMOOTH_CHEB_RAS = 0, 1, 2
+_SMOOTHERS = {"jacobi": 0, "asm": 1, "ras": 2, 0: 0, 1: 1, 2: 2}
 
 
 class sem_pmg_info(C.Structure):
@@ -99,6 +103,7 @@ _SIGS = {
     "sem_batch_step": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int)]),
     "sem_batch_poll": (C.c_int, [_P, C.c_int, C.POINTER(sem_solve_info)]),
     "sem_batch_release": (C.c_int, [_P, C.c_int]),
+    "sem_pmg_smoother_apply": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "sem_gmres_solve": (C.c_int, [_P, _P, C.c_int, _P, _P, C.POINTER(sem_solve_opts), C.POINTER(sem_solve_info), _P]),
     "sem_proj_create": (C.c_int, [_P, C.c_int, C.POINTER(_P)]),
     "sem_proj_destroy": (C.c_int, [_P]),
@@ -261,6 +266,8 @@ def pmg_opts(**kw) -> sem_pmg_opts:
                 o.rho_override = arr.ctypes.data
         elif k == "smoother_dtype":
             o.smoother_dtype = {"f32": SEM_F32, "f64": SEM_F64, SEM_F32: SEM_F32, SEM_F64: SEM_F64}[v]
+        elif k == "smoother":
+            o.smoother = _SMOOTHERS[v] if isinstance(v, str) else int(v)
         else:
             setattr(o, k, v)
     o._keep = keep
@@ -368,6 +375,10 @@ def sem_batch_poll(h, slot: int) -> dict:
 
 def sem_batch_release(h, slot: int):
     _check(load().sem_batch_release(h, slot), "sem_batch_release")
+
+
+def sem_pmg_smoother_apply(h, level, r, z, stream=None):
+    _check(load().sem_pmg_smoother_apply(h, int(level), _ptr(r), _ptr(z), _stream(stream)), "sem_pmg_smoother_apply")
 
 
 def sem_gmres_solve(mesh, pmg, K, b, x, opts: sem_solve_opts | None = None, stream=None, check=True) -> dict:

@@ -43,6 +43,7 @@ __all__ = [
     "manufactured_solution",
     "manufactured_neumann_solution",
     "relabel",
+    "rotate_elements",
     "config_meshes",
     "batched_problem_specs",
     "serving_mesh_sides",
@@ -180,6 +181,40 @@ def relabel(mesh: BoxMesh, seed: int) -> BoxMesh:
                   dirichlet=np.ascontiguousarray(mesh.dirichlet[perm]),
                   deform=mesh.deform, seed=mesh.seed, meta={"perm": perm})
     return out
+
+
+def rotate_elements(mesh: BoxMesh, seed: int) -> BoxMesh:
+    """Same mesh with each element's local (i, j, k) numbering turned by a
+    random proper rotation of the reference cube (24 choices: an even or odd
+    axis permutation combined with reflections so the orientation is kept).
+
+    Neighbouring elements then meet with every relative face orientation,
+    as in unstructured hex meshes. mesh.meta["rot"] holds the choice per element.
+    """
+    N = mesh.N
+    n = N + 1
+    rng = np.random.default_rng(seed)
+    idx = np.arange(n ** 3).reshape(n, n, n)  # [k, j, i] -> p
+    rots = []
+    for perm in ((0, 1, 2), (1, 2, 0), (2, 0, 1), (0, 2, 1), (2, 1, 0), (1, 0, 2)):
+        odd = perm in ((0, 2, 1), (2, 1, 0), (1, 0, 2))
+        for flips in ((0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1)):
+            if (sum(flips) % 2 == 1) != odd:
+                continue  # keep det = +1
+            a = idx.transpose(2, 1, 0)  # [i, j, k]
+            a = np.transpose(a, perm)
+            for ax, fl in enumerate(flips):
+                if fl:
+                    a = np.flip(a, axis=ax)
+            rots.append(np.ascontiguousarray(a.transpose(2, 1, 0)).ravel())
+    choice = rng.integers(0, len(rots), size=mesh.E)
+    src = np.stack([rots[c] for c in choice])  # new local p <- old local src[e, p]
+
+    def take(a):
+        return np.ascontiguousarray(np.take_along_axis(a, src, axis=1))
+
+    return BoxMesh(N=N, shape=mesh.shape, x=take(mesh.x), y=take(mesh.y), z=take(mesh.z), gid=take(mesh.gid),
+                   dirichlet=take(mesh.dirichlet), deform=mesh.deform, seed=mesh.seed, meta={"rot": choice})
 
 
 def random_rhs(mesh: BoxMesh, seed: int) -> np.ndarray:

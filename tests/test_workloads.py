@@ -79,3 +79,16 @@ def test_rhs_sequence_consistent_masked_and_device_path():
     # consecutive steps are close, distant ones are not
     d1 = np.max(np.abs(seq[1] - seq[0]))
     assert d1 < 0.5 * np.max(np.abs(seq[0]))
+
+
+def test_rotate_elements_keeps_the_mesh():
+    from oracle import operators as ops
+    m = wl.box_mesh(3, 2, 2, N=3, deform=0.05, seed=2)
+    r = wl.rotate_elements(m, 5)
+    assert len(set(r.meta["rot"].tolist())) > 4
+    _, _, detJ = ops.geometric_factors(3, r.x, r.y, r.z)
+    assert detJ.min() > 0
+    for e in range(m.E):
+        assert sorted(m.gid[e]) == sorted(r.gid[e])
+        order = np.argsort(r.gid[e])
+        assert np.array_equal(r.x[e][order], m.x[e][np.argsort(m.gid[e])])
