@@ -19,7 +19,9 @@ The same line reports:
   * the Poisson time-to-solution at relative residual 1e-8 for FP64 Jacobi-PCG
     and for FP64 flexible CG preconditioned by the FP32 p-multigrid V-cycle
     (N = 7 -> 3 -> 1, Chebyshev-Jacobi degree 2, coarse FP64 Jacobi-PCG to
-    1e-2) on the 48^3 mesh (and the 64^3 mesh with --solve-c2);
+    1e-2) on the 48^3 mesh (and the 64^3 mesh with --solve-c2), plus the
+    same solve with GMRES(6) and with the Chebyshev-accelerated Schwarz
+    smoothers (ASM, RAS);
   * the Helmholtz operator (A_L + lambda B) u (72 B per point) on the same
     mesh, and Helmholtz Jacobi-PCG solves on the 48^3 mesh;
   * projection onto prior solutions: per-solve time and iterations of the
@@ -125,6 +127,20 @@ def solve_pair(sem, bm, m, label, skip_pcg=False):
     out["pmg_fp32_gmres6"] = {"seconds": time.perf_counter() - t, "iters": info["iters"], "relres": info["relres"],
                               "relres_true": info["relres_true"], "coarse_iters": info["coarse_iters"]}
     log(label, "pmg-gmres6", out["pmg_fp32_gmres6"])
+    for sm in ("asm", "ras"):
+        t = time.time()
+        ps = sem.Pmg(m, smoother=sm)
+        setup_s = time.time() - t
+        sem.sem_pcg_solve(m.h, ps.h, b, x, sem.solve_opts(rtol=1e-8))  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = sem.sem_pcg_solve(m.h, ps.h, b, x, sem.solve_opts(rtol=1e-8))
+        torch.cuda.synchronize()
+        out[f"pmg_fp32_cheb_{sm}"] = {"seconds": time.perf_counter() - t, "iters": info["iters"],
+                                      "relres_true": info["relres_true"], "coarse_iters": info["coarse_iters"],
+                                      "setup_s": round(setup_s, 2), "rho": ps.info()["rho"][:2]}
+        log(label, f"pmg-{sm}", out[f"pmg_fp32_cheb_{sm}"])
+        ps.close()
     if skip_pcg:
         p.close()
         return out

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "sem_internal.h"
 
@@ -961,9 +962,10 @@ void launch_lincomb(const LincombArgs& a, hipStream_t s) {
 // overlapping Schwarz smoother with fast-diagonalization local solves
 // (Implementation, pMG smoothers, eq. fdm)
 // ---------------------------------------------------------------------------
-// One workgroup per element. Thread (a, b) of the (N+3)^2 grid owns the
-// column c = 0..N+2 of the extended box: the t-direction transforms run in
-// registers, the r and s transforms read the box staged in LDS (as in k_ax).
+// One workgroup per element; (N+3)^2 threads, each owning one grid line of
+// the extended box at a time (a c-column for the gather, the t transforms and
+// the stores; a b, c row for the r transforms; an a, c line for the s
+// transforms), with the box in LDS between directions.
 template <int N>
 struct SchCfg {
   static constexpr int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
@@ -973,12 +975,21 @@ struct SchCfg {
 
 int schwarz_blocks(int64_t E) { return (int)E; }
 
+// value of v in lane `lane` of the wave (a scalar operand)
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 template <int N, typename T, int MODE>
 __global__ __launch_bounds__(SchCfg<N>::THREADS) void k_schwarz(Table<SchwarzArgs<T>> tab) {
   using C = SchCfg<N>;
   constexpr int NP = C::NP, NP2 = C::NP2, NP3 = C::NP3, NE = C::NE, NE2 = C::NE2;
-  __shared__ T sS[3][NE2];
-  __shared__ T sL[3][NE];
   __shared__ T box[C::NE3];  // [c][b][a]
   __shared__ int sd[6][8];
   int lb;
@@ -987,12 +998,6 @@ __global__ __launch_bounds__(SchCfg<N>::THREADS) void k_schwarz(Table<SchwarzArg
   const int64_t e = lb;
   const int tid = threadIdx.x;
   if (tid < 48) sd[tid >> 3][tid & 7] = gl(a.desc)[e * 48 + tid];
-  if constexpr (MODE == 0) {
-    const SEM_GLOBAL T* Sg = gl(a.S) + e * 3 * NE2;
-    for (int k = tid; k < 3 * NE2; k += C::THREADS) sS[k / NE2][k % NE2] = Sg[k];
-    const SEM_GLOBAL T* Lg = gl(a.lam) + e * 3 * NE;
-    for (int k = tid; k < 3 * NE; k += C::THREADS) sL[k / NE][k % NE] = Lg[k];
-  }
   __syncthreads();
   const int ia = tid % NE, ib = tid / NE;
   const bool live = ib < NE;
@@ -1032,77 +1037,104 @@ __global__ __launch_bounds__(SchCfg<N>::THREADS) void k_schwarz(Table<SchwarzArg
 #pragma unroll
     for (int c = 0; c < NE; ++c) o[c] = (in_ab && c >= lo(sd[4][7]) && c <= hi(sd[5][7])) ? x[c] : T(0);
   } else {
-    // forward: S_t^T in registers
+    // Every 1D transform is done by the thread that owns the whole grid line
+    // in registers, so each LDS value feeds NE multiply-adds; the 1D
+    // matrices and eigenvalues are uniform across the workgroup and are read
+    // as scalar operands. Lines change direction through the LDS box.
+    // The element's 1D data (3 NE^2 + 3 NE values) are loaded once per wave,
+    // spread over the lanes (coalesced); each use broadcasts one lane's value
+    // as a scalar operand, so no scalar-cache or LDS traffic per use.
+    constexpr int NS = (3 * NE2 + 63) / 64, NL = (3 * NE + 63) / 64;
+    const int lane = tid & 63;
+    T sv[NS], lv[NL];
+    {
+      const SEM_GLOBAL T* Sg = gl(a.S) + e * 3 * NE2;  // [dir][ext index][mode]
+      const SEM_GLOBAL T* Lg = gl(a.lam) + e * 3 * NE;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) sv[k] = k * 64 + lane < 3 * NE2 ? Sg[k * 64 + lane] : T(0);
+#pragma unroll
+      for (int k = 0; k < NL; ++k) lv[k] = k * 64 + lane < 3 * NE ? Lg[k * 64 + lane] : T(0);
+    }
+    auto Sg = [&](int idx) -> T { return lane_value(sv[idx >> 6], idx & 63); };
+    auto Lg = [&](int idx) -> T { return lane_value(lv[idx >> 6], idx & 63); };
+    const int l1 = tid % NE, l2 = tid / NE;          // line coordinates (two of a, b, c)
     T y[NE];
+    // t forward on the gathered column (a, b) = (ia, ib)
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
       T acc = 0;
 #pragma unroll
-      for (int c = 0; c < NE; ++c) acc += sS[2][c * NE + m] * x[c];
+      for (int c = 0; c < NE; ++c) acc += Sg(2 * NE2 + c * NE + m) * x[c];
       y[m] = acc;
     }
     if (live)
 #pragma unroll
       for (int c = 0; c < NE; ++c) box[c * NE2 + ib * NE + ia] = y[c];
     __syncthreads();
-    // S_r^T along a
-    if (live)
+    // r forward on the row (b, c) = (l1, l2)
+    if (live) {
+      T* row = box + l2 * NE2 + l1 * NE;
 #pragma unroll
-      for (int c = 0; c < NE; ++c) {
+      for (int q = 0; q < NE; ++q) x[q] = row[q];
+#pragma unroll
+      for (int m = 0; m < NE; ++m) {
         T acc = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) acc += sS[0][q * NE + ia] * box[c * NE2 + ib * NE + q];
-        y[c] = acc;
+        for (int q = 0; q < NE; ++q) acc += Sg(q * NE + m) * x[q];
+        row[m] = acc;
       }
+    }
     __syncthreads();
-    if (live)
+    // s forward, divide by the eigenvalue sums, s backward on the line (a, c) = (l1, l2)
+    if (live) {
+      T* ln = box + l2 * NE2 + l1;
 #pragma unroll
-      for (int c = 0; c < NE; ++c) box[c * NE2 + ib * NE + ia] = y[c];
-    __syncthreads();
-    // S_s^T along b, then divide by the eigenvalue sums
-    if (live)
+      for (int q = 0; q < NE; ++q) x[q] = ln[q * NE];
+      static_assert(NL == 1, "eigenvalues fit in one register per lane");
+      const T lac = __shfl(lv[0], l1, 64) + __shfl(lv[0], 2 * NE + l2, 64);  // per-thread lanes
 #pragma unroll
-      for (int c = 0; c < NE; ++c) {
+      for (int m = 0; m < NE; ++m) {
         T acc = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) acc += sS[1][q * NE + ib] * box[c * NE2 + q * NE + ia];
-        const T lam = sL[0][ia] + sL[1][ib] + sL[2][c];
-        y[c] = lam > T(0) ? acc / lam : T(0);
+        for (int q = 0; q < NE; ++q) acc += Sg(NE2 + q * NE + m) * x[q];
+        const T lam = lac + Lg(NE + m);
+        T inv;
+        if constexpr (sizeof(T) == 4) inv = lam > T(0) ? __builtin_amdgcn_rcpf(lam) : T(0);
+        else inv = lam > T(0) ? T(1) / lam : T(0);
+        y[m] = acc * inv;
       }
-    __syncthreads();
-    if (live)
 #pragma unroll
-      for (int c = 0; c < NE; ++c) box[c * NE2 + ib * NE + ia] = y[c];
-    __syncthreads();
-    // backward: S_s along b
-    if (live)
-#pragma unroll
-      for (int c = 0; c < NE; ++c) {
+      for (int q = 0; q < NE; ++q) {
         T acc = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) acc += sS[1][ib * NE + q] * box[c * NE2 + q * NE + ia];
-        y[c] = acc;
+        for (int m = 0; m < NE; ++m) acc += Sg(NE2 + q * NE + m) * y[m];
+        ln[q * NE] = acc;
       }
+    }
     __syncthreads();
-    if (live)
+    // r backward on the row (b, c) = (l1, l2)
+    if (live) {
+      T* row = box + l2 * NE2 + l1 * NE;
 #pragma unroll
-      for (int c = 0; c < NE; ++c) box[c * NE2 + ib * NE + ia] = y[c];
-    __syncthreads();
-    // S_r along a
-    if (live)
+      for (int m = 0; m < NE; ++m) y[m] = row[m];
 #pragma unroll
-      for (int c = 0; c < NE; ++c) {
+      for (int q = 0; q < NE; ++q) {
         T acc = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) acc += sS[0][ia * NE + q] * box[c * NE2 + ib * NE + q];
-        y[c] = acc;
+        for (int m = 0; m < NE; ++m) acc += Sg(q * NE + m) * y[m];
+        row[q] = acc;
       }
-    // S_t in registers
+    }
+    __syncthreads();
+    // t backward on the column (a, b) = (ia, ib)
+    if (live)
+#pragma unroll
+      for (int m = 0; m < NE; ++m) y[m] = box[m * NE2 + ib * NE + ia];
 #pragma unroll
     for (int c = 0; c < NE; ++c) {
       T acc = 0;
 #pragma unroll
-      for (int m = 0; m < NE; ++m) acc += sS[2][c * NE + m] * y[m];
+      for (int m = 0; m < NE; ++m) acc += Sg(2 * NE2 + c * NE + m) * y[m];
       o[c] = acc;
     }
   }
@@ -1127,7 +1159,180 @@ __global__ __launch_bounds__(SchCfg<N>::THREADS) void k_schwarz(Table<SchwarzArg
   }
 }
 
-constexpr int kPullThreads = 256;
+// Fast-diagonalization solve on the matrix cores: one 64-lane wave per
+// element. Each 1D transform over the NE^2 grid lines of one direction is a
+// small GEMM  out[line][m] = sum_q in[line][q] S[q][m]  done as 16x16x4 MFMA
+// tiles (lines x modes x ext indices, zero-padded to 16 and to a multiple of
+// 4); the 1D matrix sits in B operand registers for the whole element, the
+// lines are read from and written back to the LDS box. One wave owns the
+// element, so successive directions need no barrier. Operand layout (both
+// precisions): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; D[i][j]
+// sits in lane j + 16 (i / 4), register i % 4 for f32, and in lane
+// j + 16 (i % 4), register i / 4 for f64.
+template <typename T>
+struct Mfma4 {
+  typedef T v __attribute__((ext_vector_type(4)));
+};
+__device__ __forceinline__ Mfma4<float>::v mfma16x16x4(float a, float b, Mfma4<float>::v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ Mfma4<double>::v mfma16x16x4(double a, double b, Mfma4<double>::v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(64) void k_schwarz_mfma(Table<SchwarzArgs<T>> tab) {
+  constexpr int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP, NE = N + 3, NE2 = NE * NE, NE3 = NE2 * NE;
+  constexpr int MT = (NE2 + 15) / 16, KS = (NE + 3) / 4;
+  static_assert(NE <= 16, "one MFMA tile spans the modes");
+  // [c][b][a] plus zero padding reached by rows beyond the grid and by the
+  // padded ext indices (largest address: t direction, q = 4 KS - 1, line 16 MT - 1)
+  constexpr int BOX = ((4 * KS - 1) * NE2 + 16 * MT > 16 * MT * NE + 4 * KS ? (4 * KS - 1) * NE2 + 16 * MT
+                                                                              : 16 * MT * NE + 4 * KS);
+  static_assert((NE - 1) * NE2 + (4 * KS - 1) * NE + 15 < BOX, "s-direction reads stay in the box");
+  __shared__ T box[BOX];
+  __shared__ T sL[3 * NE];
+  __shared__ int sd[6][8];
+  int lb;
+  const SchwarzArgs<T> a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  const int64_t e = lb;
+  const int lane = threadIdx.x;
+  if (lane < 48) sd[lane >> 3][lane & 7] = gl(a.desc)[e * 48 + lane];
+  if (lane < 3 * NE) sL[lane] = gl(a.lam)[e * 3 * NE + lane];
+  for (int k = NE3 + lane; k < BOX; k += 64) box[k] = T(0);
+  // B operands: lane holds B[k][j], k = 4 ks + lane / 16, j = lane % 16
+  const int kq = lane >> 4, jm = lane & 15;
+  T Bf[3][KS], Bb[3][KS];
+  {
+    const SEM_GLOBAL T* Sg = gl(a.S) + e * 3 * NE2;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int q = 4 * ks + kq;
+        const bool ok = q < NE && jm < NE;
+        Bf[d][ks] = ok ? Sg[d * NE2 + q * NE + jm] : T(0);  // forward: S[q][m]
+        Bb[d][ks] = ok ? Sg[d * NE2 + jm * NE + q] : T(0);  // backward: S[m][q]
+      }
+  }
+  __syncthreads();
+  const SEM_GLOBAL T* in = gl(a.in);
+  auto face = [&](int f, int u, int v) -> T {
+    const int nb = sd[f][0];
+    if (nb < 0) return T(0);
+    return in[(int64_t)nb * NP3 + sd[f][1] + u * sd[f][2] + v * sd[f][3]];
+  };
+  // gather the extended box, one (a, b) column per lane and pass
+  for (int col = lane; col < NE2; col += 64) {
+    const int ia = col % NE, ib = col / NE;
+    const bool ca = ia >= 1 && ia <= N + 1, cb = ib >= 1 && ib <= N + 1;
+    T x[NE];
+#pragma unroll
+    for (int c = 0; c < NE; ++c) x[c] = T(0);
+    if (ca && cb) {
+      const SEM_GLOBAL T* ue = in + e * NP3 + (ib - 1) * NP + (ia - 1);
+#pragma unroll
+      for (int c = 1; c <= N + 1; ++c) x[c] = ue[(c - 1) * NP2];
+      x[0] = face(4, ia - 1, ib - 1);
+      x[N + 2] = face(5, ia - 1, ib - 1);
+    } else if (!ca && cb) {
+      const int f = ia == 0 ? 0 : 1;
+#pragma unroll
+      for (int c = 1; c <= N + 1; ++c) x[c] = face(f, ib - 1, c - 1);
+    } else if (ca && !cb) {
+      const int f = ib == 0 ? 2 : 3;
+#pragma unroll
+      for (int c = 1; c <= N + 1; ++c) x[c] = face(f, ia - 1, c - 1);
+    }
+#pragma unroll
+    for (int c = 0; c < NE; ++c) box[c * NE2 + col] = x[c];
+  }
+  __syncthreads();
+  // Lines of a direction are numbered so that every LDS address is a per-lane
+  // base plus a compile-time offset: r lines (b, c) as c NE + b (address
+  // line NE + q), t lines (a, b) as b NE + a (address q NE^2 + line), and s
+  // lines (a, c) in tiles of one c with a = 0..15 (address c NE^2 + q NE + a).
+  // Rows beyond the grid read the zero padding of the box; padded ext
+  // indices q >= NE meet zero rows of B.
+  constexpr int MTS = NE;  // s tiles: one per c
+  auto transform = [&](auto dir_c, const T* B, bool scale) {
+    constexpr int DIR = decltype(dir_c)::value;
+    constexpr int TILES = DIR == 1 ? MTS : MT;
+#pragma unroll
+    for (int mt = 0; mt < TILES; ++mt) {
+      typename Mfma4<T>::v acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int q = 4 * ks + kq;
+        int ad;
+        if constexpr (DIR == 0) ad = (mt * 16 + jm) * NE + q;
+        else if constexpr (DIR == 2) ad = q * NE2 + mt * 16 + jm;
+        else ad = mt * NE2 + q * NE + jm;
+        acc = mfma16x16x4(box[ad], B[ks], acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // output row held by this lane in register r (the f32 and f64
+        // instructions spread D over lanes and registers differently)
+        const int i = sizeof(T) == 4 ? 4 * kq + r : 4 * r + kq;
+        const int lr = mt * 16 + i;
+        bool ok;
+        int ad;
+        if constexpr (DIR == 0) { ok = lr < NE2 && jm < NE; ad = lr * NE + jm; }
+        else if constexpr (DIR == 2) { ok = lr < NE2 && jm < NE; ad = jm * NE2 + lr; }
+        else { ok = i < NE && jm < NE; ad = mt * NE2 + jm * NE + i; }
+        if (ok) {
+          T v = acc[r];
+          if (scale) {  // s direction: a = i, b = jm (mode), c = mt
+            const T lam = sL[i] + sL[NE + jm] + sL[2 * NE + mt];
+            if constexpr (sizeof(T) == 4) v = lam > T(0) ? v * __builtin_amdgcn_rcpf(lam) : T(0);
+            else v = lam > T(0) ? v / lam : T(0);
+          }
+          box[ad] = v;
+        }
+      }
+    }
+  };
+  using D0 = std::integral_constant<int, 0>;
+  using D1 = std::integral_constant<int, 1>;
+  using D2 = std::integral_constant<int, 2>;
+  transform(D2{}, Bf[2], false);
+  transform(D0{}, Bf[0], false);
+  transform(D1{}, Bf[1], true);
+  transform(D1{}, Bb[1], false);
+  transform(D0{}, Bb[0], false);
+  transform(D2{}, Bb[2], false);
+  __syncthreads();
+  // own block and face layers of the local solution
+  SEM_GLOBAL T* ovl = a.ovl ? gl(a.ovl) + e * 6 * NP2 : nullptr;
+  for (int col = lane; col < NE2; col += 64) {
+    const int ia = col % NE, ib = col / NE;
+    const bool ca = ia >= 1 && ia <= N + 1, cb = ib >= 1 && ib <= N + 1;
+    if (ca && cb) {
+      SEM_GLOBAL T* oe = gl(a.out) + e * NP3 + (ib - 1) * NP + (ia - 1);
+#pragma unroll
+      for (int c = 1; c <= N + 1; ++c) oe[(c - 1) * NP2] = box[c * NE2 + col];
+      if (ovl) {
+        ovl[4 * NP2 + (ib - 1) * NP + (ia - 1)] = box[col];
+        ovl[5 * NP2 + (ib - 1) * NP + (ia - 1)] = box[(N + 2) * NE2 + col];
+      }
+    } else if (ovl && !ca && cb) {
+      const int f = ia == 0 ? 0 : 1;
+#pragma unroll
+      for (int c = 1; c <= N + 1; ++c) ovl[f * NP2 + (c - 1) * NP + (ib - 1)] = box[c * NE2 + col];
+    } else if (ovl && ca && !cb) {
+      const int f = ib == 0 ? 2 : 3;
+#pragma unroll
+      for (int c = 1; c <= N + 1; ++c) ovl[f * NP2 + (c - 1) * NP + (ia - 1)] = box[c * NE2 + col];
+    }
+  }
+}
+
+// One 64-lane wave per element and pass: pass d adds the overlaps across the
+// two faces normal to direction d. A node at depth 1 behind faces of two
+// directions is updated in two passes, so the passes are ordered by barriers.
+constexpr int kPullThreads = 64;
 
 template <int N, typename T>
 __global__ __launch_bounds__(kPullThreads) void k_schwarz_pull(Table<SchwarzPullArgs<T>> tab) {
@@ -1140,24 +1345,34 @@ __global__ __launch_bounds__(kPullThreads) void k_schwarz_pull(Table<SchwarzPull
   if (threadIdx.x < 48) sd[threadIdx.x >> 3][threadIdx.x & 7] = gl(a.desc)[e * 48 + threadIdx.x];
   __syncthreads();
   const SEM_GLOBAL T* ovl = gl(a.ovl);
+  SEM_GLOBAL T* out = gl(a.out) + e * NP3;
   auto pull = [&](int f, int u, int v) -> T {
     const int nb = sd[f][0];
     if (nb < 0) return T(0);
     return ovl[(int64_t)nb * 6 * NP2 + sd[f][4] + u * sd[f][5] + v * sd[f][6]];
   };
-  SEM_GLOBAL T* out = gl(a.out) + e * NP3;
-  for (int p = threadIdx.x; p < NP3; p += kPullThreads) {
-    const int i = p % NP, j = (p / NP) % NP, k = p / NP2;
-    const bool any = i == 1 || i == N - 1 || j == 1 || j == N - 1 || k == 1 || k == N - 1;
-    if (!any) continue;
-    T acc = 0;
-    if (i == 1) acc += pull(0, j, k);
-    if (i == N - 1) acc += pull(1, j, k);
-    if (j == 1) acc += pull(2, i, k);
-    if (j == N - 1) acc += pull(3, i, k);
-    if (k == 1) acc += pull(4, i, j);
-    if (k == N - 1) acc += pull(5, i, j);
-    out[p] += acc;
+#pragma unroll
+  for (int axis = 0; axis < 3; ++axis) {
+    const int f0 = 2 * axis, f1 = f0 + 1;
+    const bool any = sd[f0][0] >= 0 || sd[f1][0] >= 0;  // uniform
+    if (any) {
+      for (int t = threadIdx.x; t < NP2; t += kPullThreads) {
+        const int u = t % NP, v = t / NP;
+        // local index of (u, v) at depth 1 behind face f0 (low side) and f1 (high side)
+        int p0, p1;
+        if (axis == 0) { p0 = 1 + NP * u + NP2 * v; p1 = (N - 1) + NP * u + NP2 * v; }
+        else if (axis == 1) { p0 = u + NP + NP2 * v; p1 = u + NP * (N - 1) + NP2 * v; }
+        else { p0 = u + NP * v + NP2; p1 = u + NP * v + NP2 * (N - 1); }
+        const T a0 = pull(f0, u, v), a1 = pull(f1, u, v);
+        if (p0 == p1) {
+          out[p0] += a0 + a1;
+        } else {
+          out[p0] += a0;
+          out[p1] += a1;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1166,7 +1381,7 @@ void launch_schwarz(int N, int mode, const Table<SchwarzArgs<T>>& t, int64_t tot
   if (total_blocks <= 0) return;
   const dim3 g((unsigned)total_blocks);
   switch (N) {
-#define SEM_SCH_CASE(n)                                                                                     case n:                                                                                                     if (mode == 0) hipLaunchKernelGGL((k_schwarz<n, T, 0>), g, dim3(SchCfg<n>::THREADS), 0, s, t);            else hipLaunchKernelGGL((k_schwarz<n, T, 1>), g, dim3(SchCfg<n>::THREADS), 0, s, t);                      break;
+#define SEM_SCH_CASE(n) case n: if (mode == 0 && n + 3 <= 16) hipLaunchKernelGGL((k_schwarz_mfma<(n + 3 <= 16 ? n : 2), T>), g, dim3(64), 0, s, t); else if (mode == 0) hipLaunchKernelGGL((k_schwarz<n, T, 0>), g, dim3(SchCfg<n>::THREADS), 0, s, t); else hipLaunchKernelGGL((k_schwarz<n, T, 1>), g, dim3(SchCfg<n>::THREADS), 0, s, t); break;
     SEM_SCH_CASE(2) SEM_SCH_CASE(3) SEM_SCH_CASE(4) SEM_SCH_CASE(5) SEM_SCH_CASE(6) SEM_SCH_CASE(7)
     SEM_SCH_CASE(8) SEM_SCH_CASE(9) SEM_SCH_CASE(10) SEM_SCH_CASE(11) SEM_SCH_CASE(12) SEM_SCH_CASE(13)
     SEM_SCH_CASE(14) SEM_SCH_CASE(15)
