@@ -491,6 +491,44 @@ class Plan {
     gs<T>(seq, S, l, out_of, skip_mode);
   }
 
+  // one coarse CG iteration on unique DOFs of level l (parity par): p update, SpMV, x/r update
+  void cg_iteration(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, int par, const sem_pmg_opts& o) {
+    std::vector<CgArgs> args;
+    std::vector<int> st_up{0};
+    for (Slot* s : S) {
+      const MeshData& m = s->level(l);
+      CgArgs a;
+      a.n = m.n_unique;
+      a.W = m.ell_w;
+      a.col = m.ell_col.as<int>();
+      a.val = m.ell_val.as<double>();
+      a.dinv = m.dinv_u.as<double>();
+      a.x = s->cx;
+      a.r = s->cr;
+      a.w = s->cw;
+      a.p_old = s->cp;
+      a.p_new = s->cp;
+      a.partial = s->partial;
+      a.stride = s->stride;
+      a.nblk_upd = cg_update_blocks(a.n);
+      a.nblk_sp = spmv_blocks(a.n);
+      a.scal = s->scal[1];
+      a.flags = s->flags[1];
+      a.total = s->flags[0] + F_TOTAL;
+      a.par = par;
+      a.rtol = o.coarse_rtol;
+      a.maxit = o.coarse_fixed_iters > 0 ? (1 << 30) : o.coarse_maxit;
+      a.fixed = o.coarse_fixed_iters;
+      a.skip = skip(*s, 2);
+      args.push_back(a);
+      st_up.push_back(st_up.back() + (int)a.nblk_upd);
+    }
+    const int64_t tup = st_up.back();
+    add(seq, args, st_up, [tup](const Table<CgArgs>& t, hipStream_t st) { launch_cg_pupdate(t, tup, st); });
+    spmv(seq, S, l, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2, 2);
+    add(seq, args, st_up, [tup](const Table<CgArgs>& t, hipStream_t st) { launch_cg_update(t, tup, st); });
+  }
+
   // skip modes: 0 none, 1 outer done, 2 outer or coarse done
   static Skip skip(const Slot& s, int mode) {
     Skip k;
@@ -665,6 +703,12 @@ void Plan::build_vcycle(Group& g) {
     g.coarse_limit = o.coarse_fixed_iters > 0 ? o.coarse_fixed_iters : o.coarse_maxit;
     g.coarse_fixed = o.coarse_fixed_iters;
     g.coarse_check = o.coarse_check_every;
+    if (U) {
+      // a pass of the loop body is two iterations (both parities)
+      g.coarse_limit = (g.coarse_limit + 1) / 2;
+      g.coarse_fixed = g.coarse_fixed > 0 ? g.coarse_limit : 0;
+      g.coarse_check = std::max(1, g.coarse_check / 2);
+    }
     auto nvec = [c, U](Slot& s) { return vec_blocks(U ? s.level(c).n_unique : s.level(c).nloc); };
     auto cdinv = [c, U](Slot& s) { return U ? s.level(c).dinv_u.as<double>() : s.level(c).dinv64.as<double>(); };
     vec<double>(g.cinit, S, c, V_ZERO, [](Slot& s, VecArgs<double>& a) { a.x = s.cx; }, SK, U);
@@ -678,34 +722,28 @@ void Plan::build_vcycle(Group& g) {
     fin(g.cinit, S, FIN_RZ, 1, nvec, SK);
 
     if (U) {
-      // SpMV partials go to region 2; the update reduces them itself (no finalize launch)
-      spmv(g.citer, S, c, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2, 2);
+      cg_iteration(g.citer, S, c, 0, o);
+      cg_iteration(g.citer, S, c, 1, o);
     } else {
       apply_A<double>(g.citer, S, c, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2);
       fin(g.citer, S, FIN_ALPHA, 1, [c](Slot& s) { return (int64_t)ax_blocks(s.level(c).N, s.level(c).E); }, 2);
+      vec<double>(g.citer, S, c, V_PCG_UPDATE, [cdinv](Slot& s, VecArgs<double>& a) {
+        a.x = s.cx;
+        a.p = s.cp;
+        a.r = s.cr;
+        a.w = s.cw;
+        a.dinv = cdinv(s);
+        a.scal = s.scal[1];
+      }, 2);
+      fin(g.citer, S, FIN_CHECK_JACOBI, 1, nvec, 2, o.coarse_rtol,
+          o.coarse_fixed_iters > 0 ? (1 << 30) : o.coarse_maxit, o.coarse_fixed_iters, true);
+      vec<double>(g.citer, S, c, V_P_JACOBI, [cdinv](Slot& s, VecArgs<double>& a) {
+        a.p = s.cp;
+        a.r = s.cr;
+        a.dinv = cdinv(s);
+        a.scal = s.scal[1];
+      }, 2);
     }
-    vec<double>(g.citer, S, c, V_PCG_UPDATE, [cdinv, c, U](Slot& s, VecArgs<double>& a) {
-      a.x = s.cx;
-      a.p = s.cp;
-      a.r = s.cr;
-      a.w = s.cw;
-      a.dinv = cdinv(s);
-      a.scal = s.scal[1];
-      if (U) {
-        a.red_in = s.partial + 2 * s.stride;
-        a.red_n = spmv_blocks(s.level(c).n_unique);
-        a.scal_w = s.scal[1];
-        a.flags = s.flags[1];
-      }
-    }, 2, U);
-    fin(g.citer, S, FIN_CHECK_JACOBI, 1, nvec, 2, o.coarse_rtol,
-        o.coarse_fixed_iters > 0 ? (1 << 30) : o.coarse_maxit, o.coarse_fixed_iters, true);
-    vec<double>(g.citer, S, c, V_P_JACOBI, [cdinv](Slot& s, VecArgs<double>& a) {
-      a.p = s.cp;
-      a.r = s.cr;
-      a.dinv = cdinv(s);
-      a.scal = s.scal[1];
-    }, 2, U);
   }
 
   // up-sweep

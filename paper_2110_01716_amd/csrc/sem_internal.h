@@ -198,7 +198,8 @@ enum Scal : int {
   S_BB = 0, S_RZ, S_PW, S_ALPHA, S_BETA, S_RR, S_RELRES, S_ZW, S_TMP, S_RZ_NEW, S_COUNT
 };
 // integer flags of a solve stage
-enum Flag : int { F_DONE = 0, F_STATUS, F_ITERS, F_TOTAL, F_COUNT };
+// F_ITERS2: second slot of the coarse iteration counter (two-launch coarse CG)
+enum Flag : int { F_DONE = 0, F_STATUS, F_ITERS, F_TOTAL, F_ITERS2, F_COUNT };
 
 template <typename T>
 struct VecArgs {
@@ -339,6 +340,40 @@ struct SchwarzInfoArgs {
   double* lengths = nullptr;
 };
 
+// Coarse-grid Jacobi-PCG on the unique DOFs of an assembled level with no
+// finalize launches (parity `par` alternates the ring slots of rz and of the
+// iteration counter, so no launch overwrites a value its own blocks read):
+//  k_cg_pupdate: every block reduces the previous update's partials (r.r,
+//                r.D^-1 r) in a fixed order, tests convergence, forms beta,
+//                then p = D^-1 r + beta p
+//  k_spmv:       w = A p, partial p . w
+//  k_cg_update:  every block reduces the p . w partials, alpha = rz / pw;
+//                x += alpha p, r -= alpha w, partials r.r and r.D^-1 r
+struct CgArgs {
+  int64_t n = 0;
+  int W = 0;
+  const int* col = nullptr;
+  const double* val = nullptr;
+  const double* dinv = nullptr;
+  double* x = nullptr;
+  double* r = nullptr;
+  double* w = nullptr;
+  const double* p_old = nullptr;  // p before and after k_cg_pupdate (may alias)
+  double* p_new = nullptr;
+  double* partial = nullptr;  // regions 0: r.r, 1: r.D^-1 r (update), 2: p.w (spmv)
+  int64_t stride = 0;
+  int64_t nblk_upd = 0;       // blocks of k_cg_update (partials in regions 0, 1)
+  int64_t nblk_sp = 0;        // blocks of k_spmv (partials in region 2)
+  double* scal = nullptr;     // coarse stage scalars (S_BB, ring S_RZ / S_RZ_NEW, ...)
+  int* flags = nullptr;       // coarse stage flags (ring F_ITERS / F_ITERS2, ...)
+  int* total = nullptr;       // outer stage F_TOTAL (coarse iterations of the solve)
+  int par = 0;
+  double rtol = 0;
+  int maxit = 0;
+  int fixed = 0;
+  Skip skip;
+};
+
 // multi-dot: partial[k][blk] = sum over owned points of v[k] . y (k < K)
 struct MdotArgs {
   int64_t n = 0;
@@ -391,6 +426,9 @@ template <typename T>
 void launch_schwarz_pull(int N, const Table<SchwarzPullArgs<T>>& t, int64_t total_blocks, hipStream_t s);
 void launch_schwarz_info(const SchwarzInfoArgs& a, hipStream_t s);
 void launch_spmv(const Table<SpmvArgs>& t, int64_t total_blocks, hipStream_t s);
+int64_t cg_update_blocks(int64_t n);
+void launch_cg_pupdate(const Table<CgArgs>& t, int64_t total_blocks, hipStream_t s); // blocks: cg_update_blocks(n)
+void launch_cg_update(const Table<CgArgs>& t, int64_t total_blocks, hipStream_t s); // blocks: cg_update_blocks(n)
 void launch_usum(const Table<UsumArgs>& t, int64_t total_blocks, hipStream_t s);
 template <typename Tf, typename Tc>
 void launch_xfer(int dir, int Nf, int Nc, const Table<XferArgs<Tf, Tc>>& t, int64_t total_blocks,

@@ -800,7 +800,7 @@ template void launch_xfer<double, double>(int, int, int, const Table<XferArgs<do
 // ---------------------------------------------------------------------------
 // unique-DOF operators of an assembled level
 // ---------------------------------------------------------------------------
-constexpr int kSpThreads = 64;
+constexpr int kSpThreads = 256;
 
 int64_t spmv_blocks(int64_t n) { return (n + kSpThreads - 1) / kSpThreads; }
 
@@ -821,9 +821,9 @@ __global__ __launch_bounds__(kSpThreads) void k_spmv(Table<SpmvArgs> tab) {
       double v[9];
       int c[9];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        v[q] = __builtin_nontemporal_load(val + (int64_t)(k + q) * a.n);
-        c[q] = __builtin_nontemporal_load(col + (int64_t)(k + q) * a.n);
+      for (int q = 0; q < 9; ++q) {  // the matrix is re-read every coarse iteration: keep it cached
+        v[q] = val[(int64_t)(k + q) * a.n];
+        c[q] = col[(int64_t)(k + q) * a.n];
       }
       double xv[9];
 #pragma unroll
@@ -836,7 +836,8 @@ __global__ __launch_bounds__(kSpThreads) void k_spmv(Table<SpmvArgs> tab) {
     d = x[r] * y;
   }
   if (a.partial) {
-    const double s = wave_sum(d);
+    __shared__ double s_red[kSpThreads / 64];
+    const double s = block_sum<kSpThreads>(d, s_red);
     if (threadIdx.x == 0) gl(a.partial)[lb] = s;
   }
 }
@@ -844,6 +845,143 @@ __global__ __launch_bounds__(kSpThreads) void k_spmv(Table<SpmvArgs> tab) {
 void launch_spmv(const Table<SpmvArgs>& t, int64_t total_blocks, hipStream_t s) {
   if (total_blocks <= 0) return;
   hipLaunchKernelGGL(k_spmv, dim3((unsigned)total_blocks), dim3(kSpThreads), 0, s, t);
+  SEM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// coarse-grid Jacobi-PCG, two launches per iteration (see CgArgs)
+// ---------------------------------------------------------------------------
+constexpr int kCgThreads = 256;
+int64_t cg_update_blocks(int64_t n) { return (n + kCgThreads - 1) / kCgThreads; }
+
+// sum of partial[0..nb) (and partial[stride..stride+nb) if two) in a fixed
+// order; result valid in every thread
+template <int THREADS>
+__device__ __forceinline__ void block_sums2(const SEM_GLOBAL double* part, int64_t stride, int64_t nb, bool two,
+                                            double& s0, double& s1, double (*red)[THREADS / 64]) {
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t k = threadIdx.x; k < nb; k += THREADS) {
+    a0 += part[k];
+    if (two) a1 += part[stride + k];
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a0;
+    red[1][threadIdx.x >> 6] = a1;
+  }
+  __syncthreads();
+  s0 = 0.0;
+  s1 = 0.0;
+  for (int q = 0; q < THREADS / 64; ++q) {
+    s0 += red[0][q];
+    s1 += red[1][q];
+  }
+}
+
+__global__ __launch_bounds__(kCgThreads) void k_cg_pupdate(Table<CgArgs> tab) {
+  __shared__ double red[2][kCgThreads / 64];
+  __shared__ int s_go;
+  __shared__ double s_beta;
+  int lb;
+  const CgArgs a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  SEM_GLOBAL double* sc = gl(a.scal);
+  SEM_GLOBAL int* fl = gl(a.flags);
+  const int it = fl[a.par ? F_ITERS2 : F_ITERS];
+  const bool first = it == 0;
+  double rz_new = 0.0;
+  if (!first) {
+    double rr;
+    block_sums2<kCgThreads>(gl(a.partial), a.stride, a.nblk_upd, true, rr, rz_new, red);
+    if (threadIdx.x == 0) {
+      const double rel = sqrt(rr / sc[S_BB]);
+      int status = 1;
+      if (!isfinite(rr) || !isfinite(rz_new)) status = SEM_ENAN;
+      else if (a.fixed > 0) { if (it >= a.fixed) status = SEM_OK; }
+      else if (rel <= a.rtol) status = SEM_OK;
+      else if (it >= a.maxit) status = SEM_ENOCONV;
+      s_go = status == 1;
+      s_beta = rz_new / sc[a.par ? S_RZ_NEW : S_RZ];
+      if (status != 1 && lb == 0) {
+        sc[S_RR] = rr;
+        sc[S_RELRES] = rel;
+        fl[F_STATUS] = status;
+        fl[F_DONE] = 1;
+      }
+    }
+  } else if (threadIdx.x == 0) {
+    s_go = 1;
+    s_beta = 0.0;
+  }
+  __syncthreads();
+  if (!s_go) return;
+  const double beta = s_beta;
+  if (lb == 0 && threadIdx.x == 0) {
+    // ring slots the other parity reads: rz of the new p, iteration count
+    sc[a.par ? S_RZ : S_RZ_NEW] = first ? sc[S_RZ] : rz_new;
+    fl[a.par ? F_ITERS : F_ITERS2] = it + 1;
+    if (a.total) ++(*gl(a.total));
+  }
+  const int64_t i = (int64_t)lb * kCgThreads + threadIdx.x;
+  if (i < a.n) {
+    const double z = gl(a.dinv)[i] * gl(a.r)[i];
+    gl(a.p_new)[i] = first ? z : z + beta * gl(a.p_old)[i];
+  }
+}
+
+__global__ __launch_bounds__(kCgThreads) void k_cg_update(Table<CgArgs> tab) {
+  __shared__ double red[2][kCgThreads / 64];
+  int lb;
+  const CgArgs a = fetch_args(tab, blockIdx.x, lb);
+  if (skipped(a.skip)) return;
+  double pw, unused;
+  block_sums2<kCgThreads>(gl(a.partial) + 2 * a.stride, 0, a.nblk_sp, false, pw, unused, red);
+  const double alpha = gl(a.scal)[a.par ? S_RZ : S_RZ_NEW] / pw;
+  if (!isfinite(alpha)) {
+    if (lb == 0 && threadIdx.x == 0) {
+      gl(a.flags)[F_STATUS] = SEM_ENAN;
+      gl(a.flags)[F_DONE] = 1;
+    }
+    return;
+  }
+  const int64_t i = (int64_t)lb * kCgThreads + threadIdx.x;
+  double rr = 0.0, rz = 0.0;
+  if (i < a.n) {
+    const double pi = gl(a.p_new)[i];
+    gl(a.x)[i] += alpha * pi;
+    const double rn = gl(a.r)[i] - alpha * gl(a.w)[i];
+    gl(a.r)[i] = rn;
+    rr = rn * rn;
+    rz = rn * gl(a.dinv)[i] * rn;
+  }
+  __syncthreads();  // red is reused
+  double s0 = wave_sum(rr), s1 = wave_sum(rz);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = s0;
+    red[1][threadIdx.x >> 6] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t0 = 0.0, t1 = 0.0;
+    for (int q = 0; q < kCgThreads / 64; ++q) {
+      t0 += red[0][q];
+      t1 += red[1][q];
+    }
+    gl(a.partial)[lb] = t0;
+    gl(a.partial)[a.stride + lb] = t1;
+  }
+}
+
+void launch_cg_pupdate(const Table<CgArgs>& t, int64_t total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL(k_cg_pupdate, dim3((unsigned)total_blocks), dim3(kCgThreads), 0, s, t);
+  SEM_HIP(hipGetLastError());
+}
+
+void launch_cg_update(const Table<CgArgs>& t, int64_t total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL(k_cg_update, dim3((unsigned)total_blocks), dim3(kCgThreads), 0, s, t);
   SEM_HIP(hipGetLastError());
 }
 
