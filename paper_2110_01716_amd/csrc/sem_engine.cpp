@@ -554,17 +554,24 @@ void Plan::build_vcycle(Group& g) {
   const sem_pmg_opts& o = S[0]->pmg->o;
   const int K = o.cheb_degree;
   constexpr int SK = 1;  // skip when the outer solve is done
+  // with Chebyshev-Jacobi on the fine level, the entry and exit precision
+  // conversions are folded into the first and last smoothing steps
+  const bool jac0 = !S[0]->pmg->lv[0].sw.on;
+  const bool fold_in = jac0 && o.pre > 0 && K >= 2;
+  const bool fold_out = jac0 && o.post > 0;
 
-  if constexpr (sizeof(T) == 4)
-    cast<double, float>(g.head, S, 0, [](Slot& s, CastArgs<double, float>& a) {
-      a.in = s.r;
-      a.out = (float*)s.lr[0];
-    }, SK);
-  else
-    vec<double>(g.head, S, 0, V_COPY, [](Slot& s, VecArgs<double>& a) {
-      a.x = (double*)s.lr[0];
-      a.r = s.r;
-    }, SK);
+  if (!fold_in) {
+    if constexpr (sizeof(T) == 4)
+      cast<double, float>(g.head, S, 0, [](Slot& s, CastArgs<double, float>& a) {
+        a.in = s.r;
+        a.out = (float*)s.lr[0];
+      }, SK);
+    else
+      vec<double>(g.head, S, 0, V_COPY, [](Slot& s, VecArgs<double>& a) {
+        a.x = (double*)s.lr[0];
+        a.r = s.r;
+      }, SK);
+  }
 
   auto Tp = [](void* p) { return (T*)p; };
 
@@ -623,7 +630,12 @@ void Plan::build_vcycle(Group& g) {
   };
 
   // one Chebyshev sweep at level l; from_zero: x0 = 0
-  auto sweep = [&](std::vector<Fn>& seq, int l, bool from_zero) {
+  // One Chebyshev-Jacobi sweep at level l; from_zero: x0 = 0. Writes that no
+  // later step reads are left out: the last step updates x only, a sweep from
+  // zero keeps x = d implicit until its second step. in64: the sweep starts
+  // from the FP64 outer residual (V-cycle entry cast folded into the first
+  // step); out64: its last step writes the FP64 V-cycle output instead of x.
+  auto sweep = [&](std::vector<Fn>& seq, int l, bool from_zero, bool in64 = false, bool out64 = false) {
     if (S[0]->pmg->lv[l].sw.on) {
       sweep_schwarz(seq, l, from_zero);
       return;
@@ -635,16 +647,20 @@ void Plan::build_vcycle(Group& g) {
       a.d = Tp(s.ld[l]);
       a.t = Tp(s.lt[l]);
       a.dinv = dinv_of<T>(s.level(l));
+      a.in64 = s.r;
+      a.out64 = s.z;
     };
     if (from_zero) {
-      vec<T>(seq, S, l, V_CHEB_INIT0, [l, setv](Slot& s, VecArgs<T>& a) {
+      const VecOp op = K == 1 ? V_CHEB_INIT0 : (in64 ? V_CHEB_INIT0D_IN64 : V_CHEB_INIT0D);
+      vec<T>(seq, S, l, op, [l, setv](Slot& s, VecArgs<T>& a) {
         setv(s, a);
         a.c0 = 1.0 / s.pmg->lv[l].theta;
       }, SK);
     } else {
       apply_A<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.lx[l]); }, [l, Tp](Slot& s) { return Tp(s.lt[l]); },
                  false, SK);
-      vec<T>(seq, S, l, V_CHEB_INITX, [l, setv](Slot& s, VecArgs<T>& a) {
+      const VecOp op = K > 1 ? V_CHEB_INITX : (out64 ? V_CHEB_INITX_OUT64 : V_CHEB_INITX_LAST);
+      vec<T>(seq, S, l, op, [l, setv](Slot& s, VecArgs<T>& a) {
         setv(s, a);
         a.c0 = 1.0 / s.pmg->lv[l].theta;
       }, SK);
@@ -652,7 +668,10 @@ void Plan::build_vcycle(Group& g) {
     for (int j = 1; j < K; ++j) {
       apply_A<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.ld[l]); }, [l, Tp](Slot& s) { return Tp(s.lt[l]); },
                  false, SK);
-      const VecOp op = (from_zero && j == 1) ? V_CHEB_STEP0 : V_CHEB_STEP;
+      const bool last = j == K - 1;
+      VecOp op;
+      if (from_zero && j == 1) op = last ? V_CHEB_LAST0X : V_CHEB_STEP0X;
+      else op = last ? (out64 ? V_CHEB_LAST_OUT64 : V_CHEB_LAST) : V_CHEB_STEP;
       vec<T>(seq, S, l, op, [l, j, setv](Slot& s, VecArgs<T>& a) {
         setv(s, a);
         a.c1 = s.pmg->lv[l].c1[j - 1];
@@ -665,7 +684,7 @@ void Plan::build_vcycle(Group& g) {
   for (int l = 0; l + 1 < L; ++l) {
     auto& seq = g.head;
     if (o.pre > 0) {
-      sweep(seq, l, true);
+      sweep(seq, l, true, l == 0 && fold_in);
       for (int q = 1; q < o.pre; ++q) sweep(seq, l, false);
       apply_A<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.lx[l]); }, [l, Tp](Slot& s) { return Tp(s.lt[l]); },
                  false, SK);
@@ -761,19 +780,21 @@ void Plan::build_vcycle(Group& g) {
         a.xf = Tp(s.lx[l]);
       }, SK);
     }
-    for (int q = 0; q < o.post; ++q) sweep(seq, l, false);
+    for (int q = 0; q < o.post; ++q) sweep(seq, l, false, false, l == 0 && fold_out && q + 1 == o.post);
   }
 
-  if constexpr (sizeof(T) == 4)
-    cast<float, double>(g.tail, S, 0, [](Slot& s, CastArgs<float, double>& a) {
-      a.in = (const float*)s.lx[0];
-      a.out = s.z;
-    }, SK);
-  else
-    vec<double>(g.tail, S, 0, V_COPY, [](Slot& s, VecArgs<double>& a) {
-      a.x = s.z;
-      a.r = (double*)s.lx[0];
-    }, SK);
+  if (!fold_out) {
+    if constexpr (sizeof(T) == 4)
+      cast<float, double>(g.tail, S, 0, [](Slot& s, CastArgs<float, double>& a) {
+        a.in = (const float*)s.lx[0];
+        a.out = s.z;
+      }, SK);
+    else
+      vec<double>(g.tail, S, 0, V_COPY, [](Slot& s, VecArgs<double>& a) {
+        a.x = s.z;
+        a.r = (double*)s.lx[0];
+      }, SK);
+  }
 }
 
 // outer flexible CG body (after the V-cycle has produced z from r)

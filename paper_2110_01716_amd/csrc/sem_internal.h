@@ -177,6 +177,15 @@ enum VecOp : int {
   V_CHEB_INITX,       // res = r - t; d = dinv res / theta; x += d
   V_CHEB_STEP,        // res -= t; d = c1 d + c2 dinv res; x += d
   V_CHEB_STEP0,       // first step after INIT0: res = r - t; d = c1 d + c2 dinv res; x += d
+  // fused Chebyshev-Jacobi variants (no writes that nothing reads):
+  V_CHEB_INIT0D,      // d = c0 dinv r                         (x = d left implicit)
+  V_CHEB_INIT0D_IN64, // r = (T) in64; d = c0 dinv r            (V-cycle entry cast folded in)
+  V_CHEB_STEP0X,      // after INIT0D: res = r - t; dn = c1 d + c2 dinv res; x = d + dn; d = dn
+  V_CHEB_LAST0X,      // after INIT0D, last step: x = d + c1 d + c2 dinv (r - t)
+  V_CHEB_LAST,        // last step: x += c1 d + c2 dinv (res - t)
+  V_CHEB_LAST_OUT64,  // last step, V-cycle exit: out64 = (double)(x + c1 d + c2 dinv (res - t))
+  V_CHEB_INITX_LAST,  // degree 1 from x: x += c0 dinv (r - t)
+  V_CHEB_INITX_OUT64, // degree 1 from x, V-cycle exit: out64 = (double)(x + c0 dinv (r - t))
   V_RES0,             // res = r - t
   V_RES,              // res -= t
   V_CHEB_UPD,         // d = c1 d + c2 dinv r; x += d   (r: a smoother's preconditioned residual)
@@ -218,13 +227,8 @@ struct VecArgs {
   double* partial = nullptr;  // [2][stride]
   int64_t stride = 0;
   double c0 = 0, c1 = 0, c2 = 0;
-  // V_PCG_UPDATE with red_in: every block sums red_in[0..red_n) (the Ax/SpMV
-  // partials of p . Ap) in the same fixed order and takes alpha = rz / sum
-  // itself, instead of a separate finalize launch (small problems only)
-  const double* red_in = nullptr;
-  int64_t red_n = 0;
-  double* scal_w = nullptr;   // where block 0 records pw and alpha
-  int* flags = nullptr;       // breakdown: status NaN, done
+  const double* in64 = nullptr;  // V_CHEB_INIT0D_IN64
+  double* out64 = nullptr;       // V_CHEB_*_OUT64
   Skip skip;
 };
 

@@ -365,33 +365,7 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
   const int64_t base = (int64_t)lb * kVecThreads * per + threadIdx.x;
   double acc0 = 0.0, acc1 = 0.0;
   T alpha = 0, beta = 0, scale = 0;
-  if constexpr (OP == V_PCG_UPDATE) {
-    if (a.red_in) {
-      __shared__ double s_pw[kVecThreads / 64];
-      const SEM_GLOBAL double* ri = gl(a.red_in);
-      double v = 0.0;
-      for (int64_t k = threadIdx.x; k < a.red_n; k += kVecThreads) v += ri[k];
-      v = wave_sum(v);
-      if ((threadIdx.x & 63) == 0) s_pw[threadIdx.x >> 6] = v;
-      __syncthreads();
-      double pw = 0.0;
-      for (int w = 0; w < kVecThreads / 64; ++w) pw += s_pw[w];
-      double al = gl(a.scal)[S_RZ] / pw;
-      const bool bad = !isfinite(al);
-      if (bad) al = 0.0;
-      if (lb == 0 && threadIdx.x == 0) {
-        gl(a.scal_w)[S_PW] = pw;
-        gl(a.scal_w)[S_ALPHA] = al;
-        if (bad) {
-          gl(a.flags)[F_STATUS] = SEM_ENAN;
-          gl(a.flags)[F_DONE] = 1;
-        }
-      }
-      alpha = (T)al;
-    } else {
-      alpha = (T)gl(a.scal)[S_ALPHA];
-    }
-  }
+  if constexpr (OP == V_PCG_UPDATE) alpha = (T)gl(a.scal)[S_ALPHA];
   if constexpr (OP == V_P_JACOBI || OP == V_P_FLEX) beta = (T)gl(a.scal)[S_BETA];
   if constexpr (OP == V_NORMALIZE) scale = (T)gl(a.scal)[S_TMP];
   const T c0 = (T)a.c0, c1 = (T)a.c1, c2 = (T)a.c2;
@@ -445,6 +419,30 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
       const T d = c1 * Dd[l] + c2 * DINV[l] * res;
       Dd[l] = d;
       X[l] += d;
+    } else if constexpr (OP == V_CHEB_INIT0D) {
+      Dd[l] = c0 * DINV[l] * R[l];
+    } else if constexpr (OP == V_CHEB_INIT0D_IN64) {
+      const T rv = (T)gl(a.in64)[l];
+      R[l] = rv;
+      Dd[l] = c0 * DINV[l] * rv;
+    } else if constexpr (OP == V_CHEB_STEP0X) {
+      const T res = R[l] - Tt[l];
+      RES[l] = res;
+      const T dold = Dd[l];
+      const T d = c1 * dold + c2 * DINV[l] * res;
+      Dd[l] = d;
+      X[l] = dold + d;
+    } else if constexpr (OP == V_CHEB_LAST0X) {
+      const T dold = Dd[l];
+      X[l] = dold + (c1 * dold + c2 * DINV[l] * (R[l] - Tt[l]));
+    } else if constexpr (OP == V_CHEB_LAST) {
+      X[l] += c1 * Dd[l] + c2 * DINV[l] * (RES[l] - Tt[l]);
+    } else if constexpr (OP == V_CHEB_LAST_OUT64) {
+      gl(a.out64)[l] = (double)(X[l] + (c1 * Dd[l] + c2 * DINV[l] * (RES[l] - Tt[l])));
+    } else if constexpr (OP == V_CHEB_INITX_LAST) {
+      X[l] += c0 * DINV[l] * (R[l] - Tt[l]);
+    } else if constexpr (OP == V_CHEB_INITX_OUT64) {
+      gl(a.out64)[l] = (double)(X[l] + c0 * DINV[l] * (R[l] - Tt[l]));
     } else if constexpr (OP == V_RES0) {
       RES[l] = R[l] - Tt[l];
     } else if constexpr (OP == V_RES) {
@@ -509,6 +507,9 @@ void launch_vec(VecOp op, const Table<VecArgs<T>>& t, int64_t total_blocks, hipS
     SEM_VEC_CASE(V_SCALE_DINV) SEM_VEC_CASE(V_NORMALIZE) SEM_VEC_CASE(V_TRUE_RES)
     SEM_VEC_CASE(V_DIV_DINV) SEM_VEC_CASE(V_SCALE) SEM_VEC_CASE(V_AXPY)
     SEM_VEC_CASE(V_RES0) SEM_VEC_CASE(V_RES) SEM_VEC_CASE(V_CHEB_UPD) SEM_VEC_CASE(V_CHEB_UPD0) SEM_VEC_CASE(V_FILL)
+    SEM_VEC_CASE(V_CHEB_INIT0D) SEM_VEC_CASE(V_CHEB_INIT0D_IN64) SEM_VEC_CASE(V_CHEB_STEP0X)
+    SEM_VEC_CASE(V_CHEB_LAST0X) SEM_VEC_CASE(V_CHEB_LAST) SEM_VEC_CASE(V_CHEB_LAST_OUT64)
+    SEM_VEC_CASE(V_CHEB_INITX_LAST) SEM_VEC_CASE(V_CHEB_INITX_OUT64)
 #undef SEM_VEC_CASE
     default:
       fail(SEM_EINVAL, "unknown vector op %d", (int)op);

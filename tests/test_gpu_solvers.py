@@ -281,3 +281,29 @@ def test_continuous_batching_equals_alone(sem):
     for k in range(3):
         assert done[k]["status"] == 0
         assert torch.equal(alone[k], mixed[k])
+
+
+@pytest.mark.parametrize("degree,pre,post", [(1, 1, 1), (3, 1, 1), (2, 2, 1), (2, 1, 0), (2, 0, 1), (3, 2, 2)])
+def test_vcycle_schedules_match_oracle(sem, degree, pre, post):
+    """Every Chebyshev degree / sweep-count combination of the V-cycle (the
+    fused first and last smoothing steps and the folded precision
+    conversions) against the oracle, FP64 smoothing, fixed coarse iterations."""
+    import torch
+    print_case("vcycle-schedule", degree, pre, post)
+    bm = wl.box_mesh(4, 3, 3, N=5, deform=0.05, seed=19)  # 12 coarse DOFs: no exact CG breakdown in 5 steps
+    lv = _levels_oracle(bm)
+    rho = [lv[0].rho, lv[1].rho]
+    m = sem.Mesh.from_box(bm)
+    p = sem.Pmg(m, smoother_dtype="f64", rho_override=rho, coarse_fixed_iters=5, cheb_degree=degree, pre=pre,
+                post=post)
+    r = wl.random_rhs(bm, 21)
+    z = torch.zeros((bm.E, bm.Np), dtype=torch.float64, device="cuda")
+    sem.sem_pmg_apply(p.h, dev(r), z)
+    zo = opmg.vcycle(lv, r, opmg.VCycleOpts(degree=degree, pre=pre, post=post, coarse_fixed_iters=5))
+    assert rel_err(host(z), zo) <= 1e-11
+    # FP32 smoothing: same schedule within single-precision rounding
+    p32 = sem.Pmg(m, smoother_dtype="f32", rho_override=rho, coarse_fixed_iters=5, cheb_degree=degree, pre=pre,
+                  post=post)
+    z32 = torch.zeros_like(z)
+    sem.sem_pmg_apply(p32.h, dev(r), z32)
+    assert rel_err(host(z32), zo) <= 2e-5
