@@ -649,6 +649,7 @@ void Plan::build_vcycle(Group& g) {
       a.dinv = dinv_of<T>(s.level(l));
       a.in64 = s.r;
       a.out64 = s.z;
+      a.w64 = s.w;
     };
     if (from_zero) {
       const VecOp op = K == 1 ? V_CHEB_INIT0 : (in64 ? V_CHEB_INIT0D_IN64 : V_CHEB_INIT0D);
@@ -803,11 +804,15 @@ void Plan::build_flex(Group& g) {
   if (S[0]->f32()) build_vcycle<float>(g); else build_vcycle<double>(g);
   if (g.vcycle_only) return;
   auto& t = g.tail;
-  vec<double>(t, S, 0, V_DOT2, [](Slot& s, VecArgs<double>& a) {
-    a.z = s.z;
-    a.w = s.w;
-    a.r = s.r;
-  }, 1);
+  // with Chebyshev-Jacobi post-smoothing on the fine level, the V-cycle's
+  // last step already left the partials of (z, w) and (z, r)
+  const sem_pmg_opts& o = S[0]->pmg->o;
+  if (S[0]->pmg->lv[0].sw.on || o.post == 0)
+    vec<double>(t, S, 0, V_DOT2, [](Slot& s, VecArgs<double>& a) {
+      a.z = s.z;
+      a.w = s.w;
+      a.r = s.r;
+    }, 1);
   fin(t, S, FIN_BETA_FLEX, 0, [](Slot& s) { return vec_blocks(s.level(0).nloc); }, 1);
   vec<double>(t, S, 0, V_P_FLEX, [](Slot& s, VecArgs<double>& a) {
     a.p = s.p;

@@ -183,9 +183,10 @@ enum VecOp : int {
   V_CHEB_STEP0X,      // after INIT0D: res = r - t; dn = c1 d + c2 dinv res; x = d + dn; d = dn
   V_CHEB_LAST0X,      // after INIT0D, last step: x = d + c1 d + c2 dinv (r - t)
   V_CHEB_LAST,        // last step: x += c1 d + c2 dinv (res - t)
-  V_CHEB_LAST_OUT64,  // last step, V-cycle exit: out64 = (double)(x + c1 d + c2 dinv (res - t))
+  V_CHEB_LAST_OUT64,  // last step, V-cycle exit: out64 = (double)(x + c1 d + c2 dinv (res - t));
+                      //   partial0 = own out64 . w64, partial1 = own out64 . r64
   V_CHEB_INITX_LAST,  // degree 1 from x: x += c0 dinv (r - t)
-  V_CHEB_INITX_OUT64, // degree 1 from x, V-cycle exit: out64 = (double)(x + c0 dinv (r - t))
+  V_CHEB_INITX_OUT64, // degree 1 from x, V-cycle exit: out64 = (double)(x + c0 dinv (r - t)); partials as above
   V_RES0,             // res = r - t
   V_RES,              // res -= t
   V_CHEB_UPD,         // d = c1 d + c2 dinv r; x += d   (r: a smoother's preconditioned residual)
@@ -227,8 +228,9 @@ struct VecArgs {
   double* partial = nullptr;  // [2][stride]
   int64_t stride = 0;
   double c0 = 0, c1 = 0, c2 = 0;
-  const double* in64 = nullptr;  // V_CHEB_INIT0D_IN64
+  const double* in64 = nullptr;  // V_CHEB_INIT0D_IN64; the *_OUT64 ops read it as r64
   double* out64 = nullptr;       // V_CHEB_*_OUT64
+  const double* w64 = nullptr;   // V_CHEB_*_OUT64: partials of out64 . w64 and out64 . r64 (the FlexCG dots)
   Skip skip;
 };
 

@@ -438,11 +438,21 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
     } else if constexpr (OP == V_CHEB_LAST) {
       X[l] += c1 * Dd[l] + c2 * DINV[l] * (RES[l] - Tt[l]);
     } else if constexpr (OP == V_CHEB_LAST_OUT64) {
-      gl(a.out64)[l] = (double)(X[l] + (c1 * Dd[l] + c2 * DINV[l] * (RES[l] - Tt[l])));
+      const double zv = (double)(X[l] + (c1 * Dd[l] + c2 * DINV[l] * (RES[l] - Tt[l])));
+      gl(a.out64)[l] = zv;
+      if (!OWN || OWN[l]) {
+        acc0 += zv * gl(a.w64)[l];
+        acc1 += zv * gl(a.in64)[l];
+      }
     } else if constexpr (OP == V_CHEB_INITX_LAST) {
       X[l] += c0 * DINV[l] * (R[l] - Tt[l]);
     } else if constexpr (OP == V_CHEB_INITX_OUT64) {
-      gl(a.out64)[l] = (double)(X[l] + c0 * DINV[l] * (R[l] - Tt[l]));
+      const double zv = (double)(X[l] + c0 * DINV[l] * (R[l] - Tt[l]));
+      gl(a.out64)[l] = zv;
+      if (!OWN || OWN[l]) {
+        acc0 += zv * gl(a.w64)[l];
+        acc1 += zv * gl(a.in64)[l];
+      }
     } else if constexpr (OP == V_RES0) {
       RES[l] = R[l] - Tt[l];
     } else if constexpr (OP == V_RES) {
@@ -479,7 +489,7 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
     }
   }
   constexpr bool RED = (OP == V_PCG_UPDATE || OP == V_DOT2 || OP == V_DOT1 || OP == V_RZ_JACOBI ||
-                        OP == V_TRUE_RES);
+                        OP == V_TRUE_RES || OP == V_CHEB_LAST_OUT64 || OP == V_CHEB_INITX_OUT64);
   if constexpr (RED) {
     double s0 = wave_sum(acc0), s1 = wave_sum(acc1);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
