@@ -342,6 +342,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-projection", action="store_true")
     ap.add_argument("--projection-only", action="store_true")
+    ap.add_argument("--solve-repeat", type=int, default=0,
+                    help="only the 48^3 FlexCG+pMG solve, this many times, 50 ms apart (for kernel traces)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--serving-only", action="store_true")
@@ -372,6 +374,22 @@ def main():
         return
     if a.serving_only:
         print(json.dumps({"serving": bench_serving(sem)}), flush=True)
+        return
+    if a.solve_repeat > 0:
+        bm3, m3 = build_mesh(sem, wl.config_meshes()["pmg_48x48x48_N7"])
+        p3 = sem.Pmg(m3)
+        b3 = torch.from_numpy(wl.random_rhs(bm3, 2000)).to("cuda")
+        x3 = torch.empty_like(b3)
+        times = []
+        for _ in range(a.solve_repeat):
+            torch.cuda.synchronize()
+            time.sleep(0.05)  # separates the solves in a trace
+            t = time.perf_counter()
+            info = sem.sem_pcg_solve(m3.h, p3.h, b3, x3, sem.solve_opts(rtol=1e-8))
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            log("solve", info["iters"], info["coarse_iters"], round(times[-1], 5))
+        print(json.dumps({"solve_repeat": {"seconds": times, "iters": info["iters"]}}), flush=True)
         return
     if a.projection_only:
         bm3, m3 = build_mesh(sem, wl.config_meshes()["pmg_48x48x48_N7"])
