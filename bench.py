@@ -329,6 +329,60 @@ def cpu_baseline(bm_spec, budget_s=12.0):
                       f"(same construction as the workload), {reps} repetitions, one thread"}
 
 
+def oracle_timings():
+    """Host timings of the FP64 oracle (all host cores for BLAS, NumPy
+    pointwise single-threaded): Ax per point, the tiny manufactured problem
+    solved directly and by Jacobi-PCG, and the oracle's pMG-FlexCG on an
+    8^3-element N=7 box, extrapolated per DOF and iteration to the 48^3 case."""
+    import scipy.sparse.linalg as spla
+    from oracle import operators as ops, pmg as opmg, solvers as osv
+    from paper_2110_01716_amd import workloads as wl
+    out = {"cores": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    # Ax
+    for n in (4, 16):
+        bm = wl.box_mesh(n, N=7, deform=0.05 if n > 4 else 0.0, seed=1000 + n)
+        G, _, _ = ops.geometric_factors(7, bm.x, bm.y, bm.z)
+        u = np.random.default_rng(0).uniform(-1, 1, bm.x.shape)
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 3.0:
+            ops.ax_local(7, G, u)
+            reps += 1
+        dt = (time.perf_counter() - t0) / reps
+        out[f"ax_{n}^3_N7_ms"] = round(dt * 1e3, 3)
+        out[f"ax_{n}^3_N7_gdofs"] = round(bm.E * 343 / dt / 1e9, 4)
+    # tiny manufactured problem: direct and Jacobi-PCG
+    bm = wl.box_mesh(4, N=7)
+    G, B, _ = ops.geometric_factors(7, bm.x, bm.y, bm.z)
+    b = ops.assemble_rhs(7, B, bm.gid, bm.dirichlet, wl.manufactured_source(bm))
+    t0 = time.perf_counter()
+    A, ids, _ = ops.assemble(7, G, bm.gid, bm.dirichlet)
+    idsall, bu = ops.to_unique(bm.gid, b)
+    spla.spsolve(A.tocsc(), bu[np.searchsorted(idsall, ids)])
+    out["tiny_direct_s"] = round(time.perf_counter() - t0, 3)
+    dinv = ops.jacobi_inverse(7, G, bm.gid, bm.dirichlet)
+    t0 = time.perf_counter()
+    res = osv.pcg(lambda v: ops.apply_A(7, G, bm.gid, bm.dirichlet, v), lambda r: dinv * r,
+                  lambda x, y: ops.dot(bm.gid, x, y), b, rtol=1e-8)
+    out["tiny_jacobi_pcg_s"] = round(time.perf_counter() - t0, 3)
+    out["tiny_jacobi_pcg_iters"] = res.iters
+    # pMG FlexCG on 8^3, extrapolated per DOF-iteration to 48^3 (13 iterations measured on the GPU)
+    bm = wl.box_mesh(8, N=7, deform=0.05, seed=1002)
+    t0 = time.perf_counter()
+    lv = opmg.build_levels(7, bm.x, bm.y, bm.z, bm.gid, bm.dirichlet)
+    setup = time.perf_counter() - t0
+    b = wl.random_rhs(bm, 2000)
+    t0 = time.perf_counter()
+    res = opmg.pmg_flexcg(lv, b, opmg.VCycleOpts(), rtol=1e-8)
+    solve = time.perf_counter() - t0
+    per = solve / max(res.iters, 1) / bm.E
+    out["pmg_8^3_N7_setup_s"] = round(setup, 2)
+    out["pmg_8^3_N7_solve_s"] = round(solve, 2)
+    out["pmg_8^3_N7_iters"] = res.iters
+    out["pmg_48^3_N7_extrapolated_s"] = round(per * 48 ** 3 * 13, 1)
+    out["note"] = "48^3 figure extrapolated from the 8^3 run per element-iteration at 13 iterations"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,6 +396,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-projection", action="store_true")
     ap.add_argument("--projection-only", action="store_true")
+    ap.add_argument("--oracle-timings", action="store_true", help="host timings of the oracle only (no GPU)")
     ap.add_argument("--solve-repeat", type=int, default=0,
                     help="only the 48^3 FlexCG+pMG solve, this many times, 50 ms apart (for kernel traces)")
     ap.add_argument("--no-serving", action="store_true")
@@ -356,6 +411,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if a.oracle_timings:
+        print(json.dumps({"oracle_timings": oracle_timings()}), flush=True)
+        return
     import torch
     from paper_2110_01716_amd import sem, workloads as wl
     sem.load()
