@@ -1309,15 +1309,29 @@ __global__ __launch_bounds__(SchCfg<N>::THREADS) void k_schwarz(Table<SchwarzArg
 }
 
 // Fast-diagonalization solve on the matrix cores: one 64-lane wave per
-// element. Each 1D transform over the NE^2 grid lines of one direction is a
-// small GEMM  out[line][m] = sum_q in[line][q] S[q][m]  done as 16x16x4 MFMA
-// tiles (lines x modes x ext indices, zero-padded to 16 and to a multiple of
-// 4); the 1D matrix sits in B operand registers for the whole element, the
-// lines are read from and written back to the LDS box. One wave owns the
-// element, so successive directions need no barrier. Operand layout (both
-// precisions): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; D[i][j]
-// sits in lane j + 16 (i / 4), register i % 4 for f32, and in lane
-// j + 16 (i % 4), register i / 4 for f64.
+// element. The solve is six 1D transforms (S^T along a, b, c, the division
+// by the eigenvalue sums, then S along a, b, c). Each transform is a small
+// GEMM  out[line][m] = sum_q in[line][q] S[q][m]  over the NE^2 grid lines
+// of the contracted direction, done as 16x16x4 MFMA tiles (16 lines x 16
+// modes x 4 ext indices, zero-padded). Operand layout (both precisions):
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; D[i][j] sits in
+// lane j + 16 (i / 4), register i % 4 for f32, and in lane j + 16 (i % 4),
+// register i / 4 for f64.
+//
+// The box lives in one LDS buffer whose layout rotates with every
+// transform: a transform reads line-major (address line NE + q, the
+// contracted index fastest) and writes mode-major (address line + m NE^2).
+// With the lines of a transform numbered (slow, fast) = (first, second)
+// remaining index, the mode-major output is exactly the line-major input of
+// the next direction: [c][b][a] -> [m_a][c][b] -> [m_b][m_a][c] ->
+// [m_c][m_b][m_a] -> [a][m_c][m_b] -> [b][a][m_c] -> [c][b][a]. Every LDS
+// address is a per-lane base plus a compile-time offset, and the four rows a
+// lane holds in FP32 are consecutive (one 16-byte store). A transform reads
+// all of its operands into registers before it writes, so it runs in place;
+// a wave-scope fence separates the transforms (every transform reads the
+// same per-lane addresses).
+// Rows beyond the NE^2 lines and padded ext indices read the zero tail of
+// the buffer or the next line's values, which meet zero rows of B.
 template <typename T>
 struct Mfma4 {
   typedef T v __attribute__((ext_vector_type(4)));
@@ -1329,151 +1343,283 @@ __device__ __forceinline__ Mfma4<double>::v mfma16x16x4(double a, double b, Mfma
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+template <int N>
+struct SchMfma {
+  static constexpr int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
+  static constexpr int NE = N + 3, NE2 = NE * NE, NE3 = NE2 * NE;
+  static constexpr int MT = (NE2 + 15) / 16, KS = (NE + 3) / 4;
+  // largest line-major read: row 16 MT - 1, ext index 4 KS - 1
+  static constexpr int RMAX = (16 * MT - 1) * NE + 4 * KS;
+  static constexpr int BUF = ((RMAX > NE3 ? RMAX : NE3) + 3) / 4 * 4;
+};
+
 template <int N, typename T>
-__global__ __launch_bounds__(64) void k_schwarz_mfma(Table<SchwarzArgs<T>> tab) {
-  constexpr int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP, NE = N + 3, NE2 = NE * NE, NE3 = NE2 * NE;
-  constexpr int MT = (NE2 + 15) / 16, KS = (NE + 3) / 4;
+// FP32: at least five waves per SIMD (the register budget that allows);
+// FP64 keeps the compiler's choice, which holds the MFMA results in
+// accumulation registers.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1, 8)))
+void k_schwarz_mfma(Table<SchwarzArgs<T>> tab, int total) {
+  using C = SchMfma<N>;
+  constexpr int NP = C::NP, NP2 = C::NP2, NP3 = C::NP3, NE = C::NE, NE2 = C::NE2, NE3 = C::NE3;
+  constexpr int MT = C::MT, KS = C::KS, BUF = C::BUF;
+  constexpr int OWN_IT = (NP3 + 63) / 64, FACE_IT = (NP2 + 63) / 64, S_IT = (3 * NE2 + 63) / 64;
   static_assert(NE <= 16, "one MFMA tile spans the modes");
-  // [c][b][a] plus zero padding reached by rows beyond the grid and by the
-  // padded ext indices (largest address: t direction, q = 4 KS - 1, line 16 MT - 1)
-  constexpr int BOX = ((4 * KS - 1) * NE2 + 16 * MT > 16 * MT * NE + 4 * KS ? (4 * KS - 1) * NE2 + 16 * MT
-                                                                              : 16 * MT * NE + 4 * KS);
-  static_assert((NE - 1) * NE2 + (4 * KS - 1) * NE + 15 < BOX, "s-direction reads stay in the box");
-  __shared__ T box[BOX];
+  __shared__ __attribute__((aligned(16))) T box[BUF];
+  __shared__ __attribute__((aligned(16))) T sab[16 * MT];  // lambda_b + lambda_a per line of the scaled transform
   __shared__ T sL[3 * NE];
-  __shared__ int sd[6][8];
-  int lb;
-  const SchwarzArgs<T> a = fetch_args(tab, blockIdx.x, lb);
-  if (skipped(a.skip)) return;
-  const int64_t e = lb;
-  const int lane = threadIdx.x;
-  if (lane < 48) sd[lane >> 3][lane & 7] = gl(a.desc)[e * 48 + lane];
-  if (lane < 3 * NE) sL[lane] = gl(a.lam)[e * 3 * NE + lane];
-  for (int k = NE3 + lane; k < BOX; k += 64) box[k] = T(0);
-  // B operands: lane holds B[k][j], k = 4 ks + lane / 16, j = lane % 16
-  const int kq = lane >> 4, jm = lane & 15;
-  T Bf[3][KS], Bb[3][KS];
-  {
+  __shared__ T sS[3 * NE2];
+  // lane indices are redefined opaquely in every element iteration, so the
+  // per-lane LDS and global addresses are recomputed where they are used
+  // instead of being hoisted out of the loop and held in registers
+  int lane = threadIdx.x;
+  int kq = lane >> 4, jm = lane & 15;
+
+  // An element's inputs, held in registers between their load and their
+  // store to LDS: the own block, the six face layers (zero where there is no
+  // neighbour), the 1D matrices and the 1D eigenvalues.
+  struct Staged {
+    T own[OWN_IT];
+    T face[6][FACE_IT];
+    T s[S_IT];
+    T lam;
+    int faces;  // bit f set: face f has a neighbour (its staged values are valid)
+  };
+  // Loads inside the element loop may follow this kernel's own stores, so
+  // the compiler cannot use scalar loads for them; uniform values (problem
+  // arguments, face descriptors) are therefore loaded one word per lane and
+  // broadcast with readlane.
+  // The descriptor load is issued first so that waiting for it (loads
+  // complete in order) leaves the element's other loads in flight. Absent
+  // faces have zero descriptors and load element 0's first value, which the
+  // staging step skips (the box there stays zero). The skip flags are read
+  // once per problem.
+  int last_prob = -1;
+  bool last_skip = false;
+  auto fetch = [&](int vb, SchwarzArgs<T>& a, int64_t& e, bool& skip, Staged& st) {
+    int lb, prob = 0;
+    if (tab.many == nullptr) {
+      lb = vb;
+      a = tab.one;
+    } else {
+      const SEM_GLOBAL int* stt = gl(tab.starts);
+      int lo = 0, hi = tab.n;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (__builtin_amdgcn_readfirstlane(stt[mid]) <= vb) lo = mid; else hi = mid;
+      }
+      prob = lo;
+      lb = vb - __builtin_amdgcn_readfirstlane(stt[lo]);
+      constexpr int W = sizeof(SchwarzArgs<T>) / 4;
+      static_assert(sizeof(SchwarzArgs<T>) % 4 == 0 && W <= 64, "arguments fit one word per lane");
+      const SEM_GLOBAL int* src = (const SEM_GLOBAL int*)gl(tab.many + lo);
+      const int w = lane < W ? src[lane] : 0;
+      int words[W];
+#pragma unroll
+      for (int k = 0; k < W; ++k) words[k] = __builtin_amdgcn_readlane(w, k);
+      __builtin_memcpy(&a, words, sizeof(a));
+    }
+    e = lb;
+    if (prob != last_prob) {
+      last_prob = prob;
+      last_skip = skipped(a.skip);
+    }
+    skip = last_skip;
+    if (skip) return;
+    const SEM_GLOBAL T* in = gl(a.in);
+    const SEM_GLOBAL int* dsc = gl(a.desc) + e * 48;
+    const int dw = dsc[lane < 24 ? (lane >> 2) * 8 + (lane & 3) : 0];
+    const SEM_GLOBAL T* ue = in + e * NP3;
+#pragma unroll
+    for (int it = 0; it < OWN_IT; ++it) {
+      const int p = lane + 64 * it;
+      if (64 * (it + 1) <= NP3) st.own[it] = ue[p];
+      else st.own[it] = p < NP3 ? ue[p] : T(0);
+    }
     const SEM_GLOBAL T* Sg = gl(a.S) + e * 3 * NE2;
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int q = 4 * ks + kq;
-        const bool ok = q < NE && jm < NE;
-        Bf[d][ks] = ok ? Sg[d * NE2 + q * NE + jm] : T(0);  // forward: S[q][m]
-        Bb[d][ks] = ok ? Sg[d * NE2 + jm * NE + q] : T(0);  // backward: S[m][q]
-      }
-  }
-  __syncthreads();
-  const SEM_GLOBAL T* in = gl(a.in);
-  auto face = [&](int f, int u, int v) -> T {
-    const int nb = sd[f][0];
-    if (nb < 0) return T(0);
-    return in[(int64_t)nb * NP3 + sd[f][1] + u * sd[f][2] + v * sd[f][3]];
-  };
-  // gather the extended box, one (a, b) column per lane and pass
-  for (int col = lane; col < NE2; col += 64) {
-    const int ia = col % NE, ib = col / NE;
-    const bool ca = ia >= 1 && ia <= N + 1, cb = ib >= 1 && ib <= N + 1;
-    T x[NE];
-#pragma unroll
-    for (int c = 0; c < NE; ++c) x[c] = T(0);
-    if (ca && cb) {
-      const SEM_GLOBAL T* ue = in + e * NP3 + (ib - 1) * NP + (ia - 1);
-#pragma unroll
-      for (int c = 1; c <= N + 1; ++c) x[c] = ue[(c - 1) * NP2];
-      x[0] = face(4, ia - 1, ib - 1);
-      x[N + 2] = face(5, ia - 1, ib - 1);
-    } else if (!ca && cb) {
-      const int f = ia == 0 ? 0 : 1;
-#pragma unroll
-      for (int c = 1; c <= N + 1; ++c) x[c] = face(f, ib - 1, c - 1);
-    } else if (ca && !cb) {
-      const int f = ib == 0 ? 2 : 3;
-#pragma unroll
-      for (int c = 1; c <= N + 1; ++c) x[c] = face(f, ia - 1, c - 1);
+    for (int it = 0; it < S_IT; ++it) {
+      const int p = lane + 64 * it;
+      if (64 * (it + 1) <= 3 * NE2) st.s[it] = Sg[p];
+      else st.s[it] = p < 3 * NE2 ? Sg[p] : T(0);
     }
+    st.lam = gl(a.lam)[e * 3 * NE + (lane < 3 * NE ? lane : 0)];
+    st.faces = 0;
 #pragma unroll
-    for (int c = 0; c < NE; ++c) box[c * NE2 + col] = x[c];
-  }
-  __syncthreads();
-  // Lines of a direction are numbered so that every LDS address is a per-lane
-  // base plus a compile-time offset: r lines (b, c) as c NE + b (address
-  // line NE + q), t lines (a, b) as b NE + a (address q NE^2 + line), and s
-  // lines (a, c) in tiles of one c with a = 0..15 (address c NE^2 + q NE + a).
-  // Rows beyond the grid read the zero padding of the box; padded ext
-  // indices q >= NE meet zero rows of B.
-  constexpr int MTS = NE;  // s tiles: one per c
-  auto transform = [&](auto dir_c, const T* B, bool scale) {
-    constexpr int DIR = decltype(dir_c)::value;
-    constexpr int TILES = DIR == 1 ? MTS : MT;
+    for (int f = 0; f < 6; ++f) {
+      const int nb = __builtin_amdgcn_readlane(dw, 4 * f);
+      const int off = __builtin_amdgcn_readlane(dw, 4 * f + 1);
+      const int su = __builtin_amdgcn_readlane(dw, 4 * f + 2);
+      const int sv = __builtin_amdgcn_readlane(dw, 4 * f + 3);
+      const SEM_GLOBAL T* src = in + (int64_t)(nb < 0 ? 0 : nb) * NP3 + off;
 #pragma unroll
-    for (int mt = 0; mt < TILES; ++mt) {
-      typename Mfma4<T>::v acc = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int q = 4 * ks + kq;
-        int ad;
-        if constexpr (DIR == 0) ad = (mt * 16 + jm) * NE + q;
-        else if constexpr (DIR == 2) ad = q * NE2 + mt * 16 + jm;
-        else ad = mt * NE2 + q * NE + jm;
-        acc = mfma16x16x4(box[ad], B[ks], acc);
+      for (int it = 0; it < FACE_IT; ++it) {
+        const int p = lane + 64 * it;
+        const int pc = 64 * (it + 1) <= NP2 || p < NP2 ? p : 0;
+        st.face[f][it] = src[(pc % NP) * su + (pc / NP) * sv];
       }
+      if (nb >= 0) st.faces |= 1 << f;
+    }
+  };
+  // ext-box position of face f's node (u, v): a = 0 / N+2 (f = 0, 1),
+  // b = 0 / N+2 (2, 3), c = 0 / N+2 (4, 5); (u, v) run over the other two
+  auto face_pos = [](int f, int u, int v) {
+    const int base = f == 0 ? NE2 + NE : f == 1 ? NE2 + NE + (N + 2) : f == 2 ? NE2 + 1 : f == 3 ? NE2 + 1 + (N + 2) * NE
+                   : f == 4 ? NE + 1 : NE + 1 + (N + 2) * NE2;
+    return base + u * (f < 2 ? NE : 1) + v * (f < 4 ? NE2 : NE);
+  };
+  auto own_pos = [](int p) {
+    const int i = p % NP, j = (p / NP) % NP, k = p / NP2;
+    return (k + 1) * NE2 + (j + 1) * NE + (i + 1);
+  };
+
+  // one transform: line-major in, mode-major out, in place. The fence makes
+  // the previous transform's stores (by other lanes) visible: without it the
+  // compiler may reuse values a lane loaded from the same addresses before.
+  auto transform = [&](int d, bool fwd, bool scale) {
+    lds_sync<64>();
+    T B[KS];  // lane holds B[k][j], k = 4 ks + kq, j = jm: S[k][j] forward, S[j][k] backward
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // output row held by this lane in register r (the f32 and f64
-        // instructions spread D over lanes and registers differently)
-        const int i = sizeof(T) == 4 ? 4 * kq + r : 4 * r + kq;
-        const int lr = mt * 16 + i;
-        bool ok;
-        int ad;
-        if constexpr (DIR == 0) { ok = lr < NE2 && jm < NE; ad = lr * NE + jm; }
-        else if constexpr (DIR == 2) { ok = lr < NE2 && jm < NE; ad = jm * NE2 + lr; }
-        else { ok = i < NE && jm < NE; ad = mt * NE2 + jm * NE + i; }
-        if (ok) {
-          T v = acc[r];
-          if (scale) {  // s direction: a = i, b = jm (mode), c = mt
-            const T lam = sL[i] + sL[NE + jm] + sL[2 * NE + mt];
-            if constexpr (sizeof(T) == 4) v = lam > T(0) ? v * __builtin_amdgcn_rcpf(lam) : T(0);
-            else v = lam > T(0) ? v / lam : T(0);
-          }
-          box[ad] = v;
+    for (int ks = 0; ks < KS; ++ks) {
+      const int q = 4 * ks + kq;
+      const bool ok = q < NE && jm < NE;
+      const int ad = d * NE2 + (fwd ? q * NE + jm : jm * NE + q);
+      B[ks] = ok ? sS[ok ? ad : 0] : T(0);
+    }
+    T av[MT][KS];
+    const T* rd = box + jm * NE + kq;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) av[mt][ks] = rd[mt * 16 * NE + 4 * ks];
+    typename Mfma4<T>::v acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      acc[mt] = typename Mfma4<T>::v{T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) acc[mt] = mfma16x16x4(av[mt][ks], B[ks], acc[mt]);
+    }
+    // rows held by this lane: 4 kq + r (f32) or 4 r + kq (f64)
+    constexpr bool F32 = sizeof(T) == 4;
+    const int rb = F32 ? 4 * kq : kq;
+    constexpr int rs = F32 ? 1 : 4;
+    if (scale) {
+      const T lc = sL[2 * NE + (jm < NE ? jm : 0)];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const T lam = sab[mt * 16 + rb + r * rs] + lc;
+          T v = acc[mt][r];
+          if constexpr (F32) v = lam > T(0) ? v * __builtin_amdgcn_rcpf(lam) : T(0);
+          else v = lam > T(0) ? v / lam : T(0);
+          acc[mt][r] = v;
+        }
+    }
+    if (jm < NE) {
+      T* wr = box + jm * NE2 + rb;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        if (mt + 1 < MT || 16 * MT == NE2) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) wr[mt * 16 + r * rs] = acc[mt][r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (mt * 16 + rb + r * rs < NE2) wr[mt * 16 + r * rs] = acc[mt][r];
         }
       }
     }
   };
-  using D0 = std::integral_constant<int, 0>;
-  using D1 = std::integral_constant<int, 1>;
-  using D2 = std::integral_constant<int, 2>;
-  transform(D2{}, Bf[2], false);
-  transform(D0{}, Bf[0], false);
-  transform(D1{}, Bf[1], true);
-  transform(D1{}, Bb[1], false);
-  transform(D0{}, Bb[0], false);
-  transform(D2{}, Bb[2], false);
-  __syncthreads();
-  // own block and face layers of the local solution
-  SEM_GLOBAL T* ovl = a.ovl ? gl(a.ovl) + e * 6 * NP2 : nullptr;
-  for (int col = lane; col < NE2; col += 64) {
-    const int ia = col % NE, ib = col / NE;
-    const bool ca = ia >= 1 && ia <= N + 1, cb = ib >= 1 && ib <= N + 1;
-    if (ca && cb) {
-      SEM_GLOBAL T* oe = gl(a.out) + e * NP3 + (ib - 1) * NP + (ia - 1);
+
+  // Small elements keep the next element's inputs in flight during the
+  // current element's transforms; large ones (or FP64 at N = 7 and up) would
+  // need too many registers for that and load at the top of each iteration.
+  constexpr bool PRE = sizeof(T) * (OWN_IT + 6 * FACE_IT + S_IT + 1) <= 4 * 24;
+  int vb = blockIdx.x;
+  if (vb >= total) return;
+  SchwarzArgs<T> a;
+  int64_t e = 0;
+  bool skip = true;
+  Staged st;
+  if constexpr (PRE) fetch(vb, a, e, skip, st);
+  // the tail beyond the box is read as padding and never written
+  for (int k = NE3 + lane; k < BUF; k += 64) box[k] = T(0);
+  for (;;) {
+    asm volatile("" : "+v"(lane));
+    lane &= 63;  // keeps the known range (small-integer address arithmetic)
+    kq = lane >> 4;
+    jm = lane & 15;
+    if constexpr (!PRE) fetch(vb, a, e, skip, st);
+    if (!skip) {
+      // stage the element into LDS: zero box (edges and absent faces), own
+      // block, faces, 1D data; the fence orders these stores after the
+      // previous element's final reads
+      lds_sync<64>();
+      for (int k = lane; k < NE3; k += 64) box[k] = T(0);
+      lds_sync<64>();
 #pragma unroll
-      for (int c = 1; c <= N + 1; ++c) oe[(c - 1) * NP2] = box[c * NE2 + col];
-      if (ovl) {
-        ovl[4 * NP2 + (ib - 1) * NP + (ia - 1)] = box[col];
-        ovl[5 * NP2 + (ib - 1) * NP + (ia - 1)] = box[(N + 2) * NE2 + col];
+      for (int it = 0; it < OWN_IT; ++it) {
+        const int p = lane + 64 * it;
+        if (64 * (it + 1) <= NP3 || p < NP3) box[own_pos(p)] = st.own[it];
       }
-    } else if (ovl && !ca && cb) {
-      const int f = ia == 0 ? 0 : 1;
 #pragma unroll
-      for (int c = 1; c <= N + 1; ++c) ovl[f * NP2 + (c - 1) * NP + (ib - 1)] = box[c * NE2 + col];
-    } else if (ovl && ca && !cb) {
-      const int f = ib == 0 ? 2 : 3;
+      for (int f = 0; f < 6; ++f)
 #pragma unroll
-      for (int c = 1; c <= N + 1; ++c) ovl[f * NP2 + (c - 1) * NP + (ia - 1)] = box[c * NE2 + col];
+        for (int it = 0; it < FACE_IT; ++it) {
+          const int p = lane + 64 * it;
+          if ((64 * (it + 1) <= NP2 || p < NP2) && (st.faces >> f & 1)) box[face_pos(f, p % NP, p / NP)] = st.face[f][it];
+        }
+#pragma unroll
+      for (int it = 0; it < S_IT; ++it) {
+        const int p = lane + 64 * it;
+        if (64 * (it + 1) <= 3 * NE2 || p < 3 * NE2) sS[p] = st.s[it];
+      }
+      if (lane < 3 * NE) sL[lane] = st.lam;
+      lds_sync<64>();
+      for (int l = lane; l < 16 * MT; l += 64) sab[l] = l < NE2 ? sL[NE + l / NE] + sL[l % NE] : T(1);
+    }
+    // issue the next element's loads; they stay in flight during this
+    // element's transforms
+    const int vn = vb + (int)gridDim.x;
+    SchwarzArgs<T> an;
+    int64_t en = 0;
+    bool skn = true;
+    Staged sn;
+    if constexpr (PRE)
+      if (vn < total) fetch(vn, an, en, skn, sn);
+    if (!skip) {
+      transform(0, true, false);   // [c][b][a]     -> [m_a][c][b]
+      transform(1, true, false);   // [m_a][c][b]   -> [m_b][m_a][c]
+      transform(2, true, true);    // [m_b][m_a][c] -> [m_c][m_b][m_a], divided by the eigenvalue sums
+      transform(0, false, false);  // -> [a][m_c][m_b]
+      transform(1, false, false);  // -> [b][a][m_c]
+      transform(2, false, false);  // -> [c][b][a]
+      lds_sync<64>();
+      // own block and, for the additive variant, the face layers of the local solution
+      SEM_GLOBAL T* oe = gl(a.out) + e * NP3;
+#pragma unroll
+      for (int it = 0; it < OWN_IT; ++it) {
+        const int p = lane + 64 * it;
+        if (64 * (it + 1) <= NP3 || p < NP3) oe[p] = box[own_pos(p)];
+      }
+      if (a.ovl) {
+        SEM_GLOBAL T* ovl = gl(a.ovl) + e * 6 * NP2;
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+#pragma unroll
+          for (int it = 0; it < FACE_IT; ++it) {
+            const int p = lane + 64 * it;
+            if (64 * (it + 1) <= NP2 || p < NP2) ovl[f * NP2 + p] = box[face_pos(f, p % NP, p / NP)];
+          }
+      }
+    }
+    if (vn >= total) break;
+    vb = vn;
+    if constexpr (PRE) {
+      a = an;
+      e = en;
+      skip = skn;
+      st = sn;
     }
   }
 }
@@ -1525,12 +1671,30 @@ __global__ __launch_bounds__(kPullThreads) void k_schwarz_pull(Table<SchwarzPull
   }
 }
 
+// The matrix-core kernel is persistent: as many one-wave workgroups as fit on
+// the device at once, each walking the elements with a stride of the grid.
+template <int N, typename T>
+void launch_schwarz_mfma(const Table<SchwarzArgs<T>>& t, int64_t total, hipStream_t s) {
+  static const int64_t cap = [] {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_schwarz_mfma<N, T>, 64, 0) != hipSuccess ||
+        cus <= 0 || per_cu <= 0)
+      return (int64_t)1 << 30;
+    return (int64_t)cus * per_cu;
+  }();
+  if (total > INT32_MAX) fail(SEM_EINVAL, "Schwarz smoother: %lld elements exceed the launch limit", (long long)total);
+  const int64_t g = total < cap ? total : cap;
+  hipLaunchKernelGGL((k_schwarz_mfma<N, T>), dim3((unsigned)g), dim3(64), 0, s, t, (int)total);
+}
+
 template <typename T>
 void launch_schwarz(int N, int mode, const Table<SchwarzArgs<T>>& t, int64_t total_blocks, hipStream_t s) {
   if (total_blocks <= 0) return;
   const dim3 g((unsigned)total_blocks);
   switch (N) {
-#define SEM_SCH_CASE(n) case n: if (mode == 0 && n + 3 <= 16) hipLaunchKernelGGL((k_schwarz_mfma<(n + 3 <= 16 ? n : 2), T>), g, dim3(64), 0, s, t); else if (mode == 0) hipLaunchKernelGGL((k_schwarz<n, T, 0>), g, dim3(SchCfg<n>::THREADS), 0, s, t); else hipLaunchKernelGGL((k_schwarz<n, T, 1>), g, dim3(SchCfg<n>::THREADS), 0, s, t); break;
+#define SEM_SCH_CASE(n) case n: if (mode == 0 && n + 3 <= 16) launch_schwarz_mfma<(n + 3 <= 16 ? n : 2), T>(t, total_blocks, s); else if (mode == 0) hipLaunchKernelGGL((k_schwarz<n, T, 0>), g, dim3(SchCfg<n>::THREADS), 0, s, t); else hipLaunchKernelGGL((k_schwarz<n, T, 1>), g, dim3(SchCfg<n>::THREADS), 0, s, t); break;
     SEM_SCH_CASE(2) SEM_SCH_CASE(3) SEM_SCH_CASE(4) SEM_SCH_CASE(5) SEM_SCH_CASE(6) SEM_SCH_CASE(7)
     SEM_SCH_CASE(8) SEM_SCH_CASE(9) SEM_SCH_CASE(10) SEM_SCH_CASE(11) SEM_SCH_CASE(12) SEM_SCH_CASE(13)
     SEM_SCH_CASE(14) SEM_SCH_CASE(15)

@@ -52,6 +52,32 @@ def test_smoother_apply_matches_oracle(sem, variant, dtype):
         assert rel_err(host(z), zo) <= tol, (l, rel_err(host(z), zo))
 
 
+@pytest.mark.parametrize("N", [3, 7, 9])
+@pytest.mark.parametrize("variant", ["asm", "ras"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_smoother_apply_orders(sem, N, variant, dtype):
+    """Every order the matrix-core FDM kernel meets in the default hierarchies
+    (N = 3, 7, 9 and their intermediate levels 1, 3, 4): the 1D tiles span
+    one to ten 16-line row blocks and one to three 4-wide ext-index steps."""
+    import torch
+    print_case("schwarz-apply-order", N, variant, dtype)
+    bm = wl.rotate_elements(wl.box_mesh(2, 3, 2, N=N, deform=0.05, seed=53 + N), 11)
+    m = sem.Mesh.from_box(bm)
+    orders = {3: [3, 1], 7: [7, 3, 1], 9: [9, 4, 1]}[N]
+    rho = [2.0] * (len(orders) - 1)
+    p = sem.Pmg(m, orders=orders, smoother=variant, smoother_dtype=dtype, rho_override=rho)
+    lv = opmg.build_levels(bm.N, bm.x, bm.y, bm.z, bm.gid, bm.dirichlet, orders=orders, rho=rho, smoother=variant)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tol = 1e-11 if dtype == "f64" else 2e-5
+    for l in range(len(lv) - 1):
+        o = lv[l]
+        r = _consistent(o.gid, o.dirichlet, 20 + l)
+        z = torch.empty(o.x.shape, dtype=tdt, device="cuda")
+        sem.sem_pmg_smoother_apply(p.h, l, dev(r, tdt), z)
+        zo = schwarz.apply(o.extra["schwarz"], r, variant)
+        assert rel_err(host(z), zo) <= tol, (N, l, rel_err(host(z), zo))
+
+
 @pytest.mark.parametrize("variant", ["asm", "ras"])
 def test_schwarz_rho_matches_oracle(sem, variant):
     print_case("schwarz-rho", variant)
