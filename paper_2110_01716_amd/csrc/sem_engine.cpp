@@ -554,11 +554,12 @@ void Plan::build_vcycle(Group& g) {
   const sem_pmg_opts& o = S[0]->pmg->o;
   const int K = o.cheb_degree;
   constexpr int SK = 1;  // skip when the outer solve is done
-  // with Chebyshev-Jacobi on the fine level, the entry and exit precision
-  // conversions are folded into the first and last smoothing steps
+  // with Chebyshev-Jacobi on the fine level, the entry precision conversion
+  // is folded into the first smoothing step; with any smoother, the exit
+  // conversion (and the outer solver's two dot products) into the last one
   const bool jac0 = !S[0]->pmg->lv[0].sw.on;
   const bool fold_in = jac0 && o.pre > 0 && K >= 2;
-  const bool fold_out = jac0 && o.post > 0;
+  const bool fold_out = o.post > 0;
 
   if (!fold_in) {
     if constexpr (sizeof(T) == 4)
@@ -577,7 +578,7 @@ void Plan::build_vcycle(Group& g) {
 
   // one Chebyshev-accelerated Schwarz sweep: D^-1 res of the Jacobi sweep
   // becomes W S(res), computed into ls before each update
-  auto sweep_schwarz = [&](std::vector<Fn>& seq, int l, bool from_zero) {
+  auto sweep_schwarz = [&](std::vector<Fn>& seq, int l, bool from_zero, bool out64) {
     const auto wts = [l](Slot& s) -> const T* {
       if constexpr (sizeof(T) == 8) return s.pmg->lv[l].sw.w64.template as<double>();
       else return s.pmg->lv[l].sw.w32.template as<float>();
@@ -589,6 +590,9 @@ void Plan::build_vcycle(Group& g) {
       a.d = Tp(s.ld[l]);
       a.t = Tp(s.lt[l]);
       a.dinv = wts(s);
+      a.in64 = s.r;
+      a.out64 = s.z;
+      a.w64 = s.w;
     };
     const auto out_s = [l, Tp](Slot& s) { return Tp(s.ls[l]); };
     if (from_zero) {
@@ -606,7 +610,7 @@ void Plan::build_vcycle(Group& g) {
         a.t = Tp(s.lt[l]);
       }, SK);
       schwarz<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.lres[l]); }, out_s, SK);
-      vec<T>(seq, S, l, V_CHEB_UPD0, [l, setv](Slot& s, VecArgs<T>& a) {
+      vec<T>(seq, S, l, out64 && K == 1 ? V_CHEB_UPD0_OUT64 : V_CHEB_UPD0, [l, setv](Slot& s, VecArgs<T>& a) {
         setv(s, a);
         a.c2 = 1.0 / s.pmg->lv[l].theta;
       }, SK);
@@ -621,7 +625,7 @@ void Plan::build_vcycle(Group& g) {
         a.t = Tp(s.lt[l]);
       }, SK);
       schwarz<T>(seq, S, l, [l, Tp](Slot& s) { return (const T*)Tp(s.lres[l]); }, out_s, SK);
-      vec<T>(seq, S, l, V_CHEB_UPD, [l, j, setv](Slot& s, VecArgs<T>& a) {
+      vec<T>(seq, S, l, out64 && j == K - 1 ? V_CHEB_UPD_OUT64 : V_CHEB_UPD, [l, j, setv](Slot& s, VecArgs<T>& a) {
         setv(s, a);
         a.c1 = s.pmg->lv[l].c1[j - 1];
         a.c2 = s.pmg->lv[l].c2[j - 1];
@@ -637,7 +641,7 @@ void Plan::build_vcycle(Group& g) {
   // step); out64: its last step writes the FP64 V-cycle output instead of x.
   auto sweep = [&](std::vector<Fn>& seq, int l, bool from_zero, bool in64 = false, bool out64 = false) {
     if (S[0]->pmg->lv[l].sw.on) {
-      sweep_schwarz(seq, l, from_zero);
+      sweep_schwarz(seq, l, from_zero, out64);
       return;
     }
     const auto setv = [l, Tp](Slot& s, VecArgs<T>& a) {
@@ -804,10 +808,10 @@ void Plan::build_flex(Group& g) {
   if (S[0]->f32()) build_vcycle<float>(g); else build_vcycle<double>(g);
   if (g.vcycle_only) return;
   auto& t = g.tail;
-  // with Chebyshev-Jacobi post-smoothing on the fine level, the V-cycle's
-  // last step already left the partials of (z, w) and (z, r)
+  // with post-smoothing on the fine level, the V-cycle's last step already
+  // left the partials of (z, w) and (z, r)
   const sem_pmg_opts& o = S[0]->pmg->o;
-  if (S[0]->pmg->lv[0].sw.on || o.post == 0)
+  if (o.post == 0)
     vec<double>(t, S, 0, V_DOT2, [](Slot& s, VecArgs<double>& a) {
       a.z = s.z;
       a.w = s.w;

@@ -191,6 +191,8 @@ enum VecOp : int {
   V_RES,              // res -= t
   V_CHEB_UPD,         // d = c1 d + c2 dinv r; x += d   (r: a smoother's preconditioned residual)
   V_CHEB_UPD0,        // d = c2 dinv r; x += d
+  V_CHEB_UPD_OUT64,   // last Schwarz step, V-cycle exit: out64 = (double)(x + c1 d + c2 dinv r); partials as above
+  V_CHEB_UPD0_OUT64,  // degree 1: out64 = (double)(x + c2 dinv r); partials as above
   V_ZERO,             // x = 0
   V_FILL,             // x = c0
   V_COPY,             // x = r

@@ -465,6 +465,16 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
       const T d = c2 * DINV[l] * R[l];
       Dd[l] = d;
       X[l] += d;
+    } else if constexpr (OP == V_CHEB_UPD_OUT64 || OP == V_CHEB_UPD0_OUT64) {
+      T d;
+      if constexpr (OP == V_CHEB_UPD_OUT64) d = c1 * Dd[l] + c2 * DINV[l] * R[l];  // as V_CHEB_UPD
+      else d = c2 * DINV[l] * R[l];
+      const double zv = (double)(X[l] + d);
+      gl(a.out64)[l] = zv;
+      if (!OWN || OWN[l]) {
+        acc0 += zv * gl(a.w64)[l];
+        acc1 += zv * gl(a.in64)[l];
+      }
     } else if constexpr (OP == V_ZERO) {
       X[l] = T(0);
     } else if constexpr (OP == V_FILL) {
@@ -489,7 +499,8 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
     }
   }
   constexpr bool RED = (OP == V_PCG_UPDATE || OP == V_DOT2 || OP == V_DOT1 || OP == V_RZ_JACOBI ||
-                        OP == V_TRUE_RES || OP == V_CHEB_LAST_OUT64 || OP == V_CHEB_INITX_OUT64);
+                        OP == V_TRUE_RES || OP == V_CHEB_LAST_OUT64 || OP == V_CHEB_INITX_OUT64 ||
+                        OP == V_CHEB_UPD_OUT64 || OP == V_CHEB_UPD0_OUT64);
   if constexpr (RED) {
     double s0 = wave_sum(acc0), s1 = wave_sum(acc1);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -520,6 +531,7 @@ void launch_vec(VecOp op, const Table<VecArgs<T>>& t, int64_t total_blocks, hipS
     SEM_VEC_CASE(V_CHEB_INIT0D) SEM_VEC_CASE(V_CHEB_INIT0D_IN64) SEM_VEC_CASE(V_CHEB_STEP0X)
     SEM_VEC_CASE(V_CHEB_LAST0X) SEM_VEC_CASE(V_CHEB_LAST) SEM_VEC_CASE(V_CHEB_LAST_OUT64)
     SEM_VEC_CASE(V_CHEB_INITX_LAST) SEM_VEC_CASE(V_CHEB_INITX_OUT64)
+    SEM_VEC_CASE(V_CHEB_UPD_OUT64) SEM_VEC_CASE(V_CHEB_UPD0_OUT64)
 #undef SEM_VEC_CASE
     default:
       fail(SEM_EINVAL, "unknown vector op %d", (int)op);
