@@ -688,7 +688,9 @@ void launch_fin(FinOp op, const Table<FinArgs>& t, int nprob, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // pMG transfers: out = (M x M x M) in per element, M is NO x NI
 // ---------------------------------------------------------------------------
-constexpr int kXferThreads = 256;
+// one wave per block: an element's loads are all issued before its first
+// LDS hand-off, and the hand-offs between the three passes stay inside a wave
+constexpr int kXferThreads = 64;
 
 template <int NI, int NO>
 struct XferCfg {
@@ -750,6 +752,7 @@ __global__ __launch_bounds__(kXferThreads) void k_xfer(Table<XferArgs<Tf, Tc>> t
   if (skipped(a.skip)) return;
   const int64_t e_first = (int64_t)lb * C::EPB;
   for (int t = threadIdx.x; t < NO * NI; t += kXferThreads) sM[t] = (Tf)Mg[t];
+#pragma unroll
   for (int t = threadIdx.x; t < C::EPB * C::S0; t += kXferThreads) {
     const int el = t / C::S0, r = t - el * C::S0;
     const int64_t e = e_first + el;
@@ -768,6 +771,7 @@ __global__ __launch_bounds__(kXferThreads) void k_xfer(Table<XferArgs<Tf, Tc>> t
   }
   __syncthreads();
   tensor3<NI, NO, Tf>(sM, s0, s1, s2, s3);
+#pragma unroll
   for (int t = threadIdx.x; t < C::EPB * C::S3; t += kXferThreads) {
     const int el = t / C::S3, r = t - el * C::S3;
     const int64_t e = e_first + el;
