@@ -248,7 +248,9 @@ void build_assembled(MeshData& m, hipStream_t s) {
   cnt.alloc(sizeof(int) * (nun + 1));
   rowoff.alloc(sizeof(int) * (nun + 1));
   SEM_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (nun + 1), s));
-  hipLaunchKernelGGL(k_row_count, dim3(nb(nent)), dim3(kT), 0, s, nent, ent_row.as<int>(), cnt.as<int>());
+  // a level whose every node is Dirichlet has no entries (and no launch)
+  if (nent > 0)
+    hipLaunchKernelGGL(k_row_count, dim3(nb(nent)), dim3(kT), 0, s, nent, ent_row.as<int>(), cnt.as<int>());
   with_temp([&](void* tmp, size_t& bytes) {
     return rocprim::exclusive_scan(tmp, bytes, cnt.as<int>(), rowoff.as<int>(), 0, (size_t)nun + 1,
                                    rocprim::plus<int>(), s);

@@ -1250,13 +1250,15 @@ __global__ __launch_bounds__(SchCfg<N>::THREADS) void k_schwarz(Table<SchwarzArg
       }
     }
     __syncthreads();
-    // s forward, divide by the eigenvalue sums, s backward on the line (a, c) = (l1, l2)
+    // s forward, divide by the eigenvalue sums, s backward on the line (a, c) = (l1, l2).
+    // The eigenvalue shuffle runs with every lane active: a lane outside the
+    // grid may be the source another lane reads.
+    static_assert(NL == 1, "eigenvalues fit in one register per lane");
+    const T lac = __shfl(lv[0], l1 < NE ? l1 : 0, 64) + __shfl(lv[0], 2 * NE + (l2 < NE ? l2 : 0), 64);
     if (live) {
       T* ln = box + l2 * NE2 + l1;
 #pragma unroll
       for (int q = 0; q < NE; ++q) x[q] = ln[q * NE];
-      static_assert(NL == 1, "eigenvalues fit in one register per lane");
-      const T lac = __shfl(lv[0], l1, 64) + __shfl(lv[0], 2 * NE + l2, 64);  // per-thread lanes
 #pragma unroll
       for (int m = 0; m < NE; ++m) {
         T acc = 0;

@@ -52,18 +52,21 @@ def test_smoother_apply_matches_oracle(sem, variant, dtype):
         assert rel_err(host(z), zo) <= tol, (l, rel_err(host(z), zo))
 
 
-@pytest.mark.parametrize("N", [3, 7, 9])
+@pytest.mark.parametrize("N", [3, 7, 9, 13, 14])
 @pytest.mark.parametrize("variant", ["asm", "ras"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_smoother_apply_orders(sem, N, variant, dtype):
     """Every order the matrix-core FDM kernel meets in the default hierarchies
     (N = 3, 7, 9 and their intermediate levels 1, 3, 4): the 1D tiles span
-    one to ten 16-line row blocks and one to three 4-wide ext-index steps."""
+    one to ten 16-line row blocks and one to three 4-wide ext-index steps.
+    N = 13 is the largest order the 16-wide tiles hold (sixteen row blocks,
+    four ext-index steps); N = 14 takes the vector-unit kernel."""
     import torch
     print_case("schwarz-apply-order", N, variant, dtype)
-    bm = wl.rotate_elements(wl.box_mesh(2, 3, 2, N=N, deform=0.05, seed=53 + N), 11)
+    shape = (2, 3, 2) if N < 13 else (2, 2, 1)
+    bm = wl.rotate_elements(wl.box_mesh(*shape, N=N, deform=0.05, seed=53 + N), 11)
     m = sem.Mesh.from_box(bm)
-    orders = {3: [3, 1], 7: [7, 3, 1], 9: [9, 4, 1]}[N]
+    orders = {3: [3, 1], 7: [7, 3, 1], 9: [9, 4, 1], 13: [13, 1], 14: [14, 1]}[N]
     rho = [2.0] * (len(orders) - 1)
     p = sem.Pmg(m, orders=orders, smoother=variant, smoother_dtype=dtype, rho_override=rho)
     lv = opmg.build_levels(bm.N, bm.x, bm.y, bm.z, bm.gid, bm.dirichlet, orders=orders, rho=rho, smoother=variant)

@@ -219,6 +219,24 @@ def test_pmg_flexcg_solution(sem, dtype):
     assert info["coarse_iters"] > 0
 
 
+@pytest.mark.parametrize("smoother", ["jacobi", "ras"])
+def test_pmg_single_layer_mesh(sem, smoother):
+    """Degenerate hierarchy: one element across z, so every node of the N=1
+    coarse level lies on the Dirichlet boundary and the coarse system is
+    empty. The coarse correction is zero and the smoothers carry the solve."""
+    import torch
+    print_case("single-layer", smoother)
+    bm = wl.box_mesh(3, 2, 1, N=7, deform=0.05, seed=12)
+    m = sem.Mesh.from_box(bm)
+    p = sem.Pmg(m, smoother=smoother)
+    b = wl.random_rhs(bm, 3)
+    bd = dev(b)
+    x = torch.empty_like(bd)
+    info = sem.sem_pcg_solve(m.h, p.h, bd, x, sem.solve_opts(rtol=1e-10, maxit=200))
+    assert info["status"] == 0, info
+    assert rel_err(host(x), direct_solution(bm, b)) <= 1e-8
+
+
 def test_batched_equals_alone_bitwise(sem):
     import torch
     print_case("batched")
