@@ -219,14 +219,16 @@ def test_pmg_flexcg_solution(sem, dtype):
     assert info["coarse_iters"] > 0
 
 
+@pytest.mark.parametrize("shape", [(3, 2, 1), (1, 1, 1)])
 @pytest.mark.parametrize("smoother", ["jacobi", "ras"])
-def test_pmg_single_layer_mesh(sem, smoother):
-    """Degenerate hierarchy: one element across z, so every node of the N=1
-    coarse level lies on the Dirichlet boundary and the coarse system is
-    empty. The coarse correction is zero and the smoothers carry the solve."""
+def test_pmg_single_layer_mesh(sem, smoother, shape):
+    """Degenerate hierarchy: one element across z (or a single element), so
+    every node of the N=1 coarse level lies on the Dirichlet boundary and the
+    coarse system is empty. The coarse correction is zero and the smoothers
+    carry the solve; a single element also has no shared nodes at all."""
     import torch
-    print_case("single-layer", smoother)
-    bm = wl.box_mesh(3, 2, 1, N=7, deform=0.05, seed=12)
+    print_case("single-layer", smoother, shape)
+    bm = wl.box_mesh(*shape, N=7, deform=0.05, seed=12)
     m = sem.Mesh.from_box(bm)
     p = sem.Pmg(m, smoother=smoother)
     b = wl.random_rhs(bm, 3)
