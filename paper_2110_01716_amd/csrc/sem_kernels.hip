@@ -16,12 +16,23 @@
 //              scalar recurrences (alpha, beta, convergence tests).
 //  * k_xfer    pMG prolongation (J x J x J) and restriction (transpose), sum
 //              factorised in LDS (Implementation, pMG paragraph).
+//  * k_spmv, k_cg_pupdate, k_cg_update
+//              coarse-level Jacobi-PCG on the assembled N=1 operator.
+//  * k_schwarz_mfma, k_schwarz, k_schwarz_pull
+//              overlapping Schwarz smoother: fast-diagonalization solve on
+//              each element's extended box (Implementation, pMG smoothers,
+//              eq. fdm) on the matrix cores, or on the vector units for
+//              N >= 14; the additive variant's overlap exchange.
+//  * k_mdot, k_mfin, k_lincomb
+//              multi-dot products and linear combinations of up to 64
+//              vectors (GMRES Arnoldi steps, projection onto prior solutions).
 //  * setup     geometric factors, Jacobi diagonal, start vectors, coordinates.
 //
 // Every kernel accepts a Table: either inline arguments for one problem or a
 // device array of per-problem arguments with block prefix offsets, so one
 // launch can serve many independent solves (blocks never straddle problems,
-// so each problem's arithmetic is independent of the others).
+// so each problem's arithmetic is independent of the others; the persistent
+// Schwarz kernel walks elements of several problems, one element at a time).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
