@@ -72,8 +72,12 @@ def pcg(apply_A, apply_M, dot, b, rtol=1e-8, maxit=10000, fixed_iters=None):
     return SolveResult(x, it, relres, hist)
 
 
-def flexcg(apply_A, apply_M, dot, b, rtol=1e-8, maxit=1000, fixed_iters=None):
-    """Flexible CG (Polak-Ribiere beta) with x0 = 0."""
+def flexcg(apply_A, apply_M, dot, b, rtol=1e-8, maxit=1000, fixed_iters=None, callback=None):
+    """Flexible CG (Polak-Ribiere beta) with x0 = 0.
+
+    callback(k, p, w), if given, sees every search direction p_k and w = A p_k
+    (k = 0, 1, ...) as soon as w is formed.
+    """
     x = np.zeros_like(b)
     r = b.copy()
     bnorm = np.sqrt(dot(b, b))
@@ -88,6 +92,8 @@ def flexcg(apply_A, apply_M, dot, b, rtol=1e-8, maxit=1000, fixed_iters=None):
     relres = 1.0
     while it < limit:
         w = apply_A(p)
+        if callback is not None:
+            callback(it, p, w)
         alpha = rz / dot(p, w)
         x = x + alpha * p
         r_old = r

@@ -187,3 +187,45 @@ def test_helmholtz_adds_mass():
     ma = wl.box_mesh(2, N=N)
     _, Ba, _ = ops.geometric_factors(N, ma.x, ma.y, ma.z)
     assert abs(np.sum(Ba * ma.x ** 2) - 1 / 3) < 1e-14
+
+
+def _linear_field_forms(N, m, G):
+    """[E, 3, 3]: x_a^T A^e x_b per element for the coordinate fields x, y, z."""
+    X = (m.x, m.y, m.z)
+    AX = [ops.ax_local(N, G, c) for c in X]
+    return np.stack([np.stack([np.sum(X[a] * AX[b], axis=1) for b in range(3)], axis=1) for a in range(3)],
+                    axis=1)
+
+
+@pytest.mark.parametrize("N", [2, 5, 7])
+def test_linear_fields_on_deformed_mesh(N):
+    # The coordinate fields x_a are exactly in the isoparametric space, so the
+    # discrete gradient of x_a is the unit vector e_a at every quadrature point
+    # and the weak form gives x_a^T A^e x_b = delta_ab * sum_p B_p on every
+    # element, for any (non-affine) deformation. A geometric factor built from
+    # a transposed inverse Jacobian, a swapped pair of G slots or a wrong
+    # weight breaks it.
+    m = wl.box_mesh(3, N=N, deform=0.05, seed=13, dirichlet=False)
+    G, B, _ = ops.geometric_factors(N, m.x, m.y, m.z)
+    F = _linear_field_forms(N, m, G)
+    vol = B.sum(axis=1)
+    for a in range(3):
+        for b in range(3):
+            want = vol if a == b else np.zeros_like(vol)
+            assert np.max(np.abs(F[:, a, b] - want)) <= 1e-12 * vol.max(), (a, b)
+    # the deformation is genuinely non-affine: J varies inside elements
+    assert np.ptp(G[:, 1]) > 1e-3 * np.abs(G[:, 0]).max()
+
+
+def test_linear_field_identity_rejects_transposed_inverse(monkeypatch):
+    # a plausible mistake planted in the oracle (d r / d x read as the
+    # transpose of the inverse Jacobian) must fail the identity above
+    N = 5
+    m = wl.box_mesh(3, N=N, deform=0.05, seed=13, dirichlet=False)
+    inv = np.linalg.inv
+    monkeypatch.setattr(np.linalg, "inv", lambda a: np.swapaxes(inv(a), -1, -2))
+    G, B, _ = ops.geometric_factors(N, m.x, m.y, m.z)
+    F = _linear_field_forms(N, m, G)
+    vol = B.sum(axis=1)
+    dev = max(np.max(np.abs(F[:, a, b] - (vol if a == b else 0.0))) for a in range(3) for b in range(3))
+    assert dev > 1e-4 * vol.max()

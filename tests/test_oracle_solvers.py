@@ -183,3 +183,45 @@ def test_pmg_flexcg_solution_matches_direct():
     x = _direct(m, N, levels[0].G, b)
     assert np.max(np.abs(res.x - x)) <= 1e-10 * np.max(np.abs(x))
     assert res.iters < 25
+
+
+def _varying_preconditioner(dinv, seed=0):
+    rng = np.random.default_rng(seed)
+
+    def M(v):  # a different SPD scaling at every application
+        wgt = 1.0 + 0.5 * np.cos(np.arange(v.size) * rng.uniform(0.1, 3.0)).reshape(v.shape) ** 2
+        return dinv * v * wgt
+    return M
+
+
+def _local_a_orthogonality(flex, N=4, iters=10):
+    """max_k |(p_{k+1}, A p_k)| / (|p_{k+1}|_A |p_k|_A) of a flexible-CG run."""
+    m, G, B, A, dot, dinv = _setup(3, N)
+    b = wl.random_rhs(m, 21)
+    seen = []
+    flex(A, _varying_preconditioner(dinv), dot, b, fixed_iters=iters,
+         callback=lambda k, p, w: seen.append((p.copy(), w.copy())))
+    cos = []
+    for (p0, w0), (p1, w1) in zip(seen, seen[1:]):
+        cos.append(abs(dot(p1, w0)) / np.sqrt(dot(p0, w0) * dot(p1, w1)))
+    return max(cos)
+
+
+def test_flexcg_polak_ribiere_keeps_local_a_orthogonality():
+    # With beta = (z_new, r_new - r_old) / (z_old, r_old) and r_new - r_old =
+    # -alpha A p_k, beta equals -(z_new, A p_k) / (p_k, A p_k): the new search
+    # direction is A-orthogonal to the previous one whatever the
+    # preconditioner did (Notay 2000). Fletcher-Reeves' (z_new, r_new) /
+    # (z_old, r_old) equals it only when M is fixed.
+    assert _local_a_orthogonality(solvers.flexcg) <= 1e-10
+
+
+def test_local_a_orthogonality_rejects_fletcher_reeves():
+    # the same check on a copy of the oracle's flexible CG with the
+    # Fletcher-Reeves beta planted in it must fail
+    import inspect
+    src = inspect.getsource(solvers.flexcg)
+    assert "dot(z, r - r_old) / rz" in src
+    ns = dict(solvers.__dict__)
+    exec(compile(src.replace("dot(z, r - r_old) / rz", "dot(z, r) / rz"), "<mutated flexcg>", "exec"), ns)
+    assert _local_a_orthogonality(ns["flexcg"]) > 1e-3
