@@ -102,7 +102,125 @@ def time_ax(sem, m, E, Np, steps, warmup, lam=None):
     return wall, ms
 
 
-def solve_pair(sem, bm, m, label, skip_pcg=False):
+def time_stream(sem, n, steps, warmup):
+    """Event-timed bandwidth probe (sem_stream) on n doubles per array: copy
+    (16 B per element), STREAM triad (24 B) and the FP64 Ax read:write mix of
+    seven streams in, one out (64 B, as Ax per local point)."""
+    import torch
+    n -= n % 2
+    src = torch.empty((7, n), dtype=torch.float64, device="cuda").uniform_(-1, 1)
+    dst = torch.empty(n, dtype=torch.float64, device="cuda")
+    out = {"elements": n}
+    for name, nin, bpe in (("copy", 1, 16), ("triad", 2, 24), ("ax_mix_7r1w", 7, 64)):
+        for _ in range(warmup):
+            sem.sem_stream(nin, src, dst, 0.5, n)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in ev:
+            a.record()
+            sem.sem_stream(nin, src, dst, 0.5, n)
+            b.record()
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        out[name] = {"bytes_per_element": bpe, "ms_mean": round(ms, 4), "GBs": round(bpe * n / (ms * 1e-3) / 1e9, 1)}
+    del src, dst
+    return out
+
+
+def load_xstar_samples(n):
+    """Sampled FP64 oracle solution of the n^3 mixed-precision workload
+    (tests/golden, written by make_oracle_solution_samples.py), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"pmg_{n}x{n}x{n}_N7_rhs2000_xstar_samples.txt")
+    if not os.path.exists(path):
+        return None
+    meta, idx, val = {}, [], []
+    for line in open(path):
+        if line.startswith("#"):
+            parts = line[1:].split()
+            if len(parts) == 2:
+                try:
+                    meta[parts[0]] = float(parts[1])
+                except ValueError:
+                    pass
+            continue
+        i, v = line.split()
+        idx.append(int(i))
+        val.append(float(v))
+    return {"meta": meta, "idx": np.array(idx, dtype=np.int64), "val": np.array(val), "file": os.path.relpath(path, ROOT)}
+
+
+def solution_errors(x, samples, xref):
+    """Relative max-norm error of x against the oracle's x* at the sampled
+    DOFs (scaled by max |x*| over all DOFs) and against a full reference."""
+    import torch
+    e = {}
+    if samples is not None:
+        it = torch.from_numpy(samples["idx"]).to(x.device)
+        xs = x.reshape(-1)[it].cpu().numpy()
+        e["err_vs_oracle_sampled"] = float(np.max(np.abs(xs - samples["val"])) / samples["meta"]["xstar_max_abs"])
+    if xref is not None:
+        e["err_vs_ref_max"] = float((x - xref).abs().max() / xref.abs().max())
+    return e
+
+
+def time_to_error(sem, m, p, b, x, samples, xref, rtols, target=1e-8, maxit=None):
+    """Solve at decreasing rtol until the solution error (max of the sampled
+    oracle error and the full-reference error) is <= target; every solve is
+    timed from the call to its return. Returns the per-rtol records and the
+    first rtol that meets the target with its time."""
+    import torch
+    runs = []
+    hit = None
+    for rtol in rtols:
+        o = sem.solve_opts(rtol=rtol, maxit=maxit) if maxit else sem.solve_opts(rtol=rtol)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = sem.sem_pcg_solve(m.h, p.h if p is not None else None, b, x, o)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        rec = {"rtol": rtol, "seconds": round(sec, 5), "iters": info["iters"], "relres_true": info["relres_true"]}
+        rec.update(solution_errors(x, samples, xref))
+        runs.append(rec)
+        err = max(v for k, v in rec.items() if k.startswith("err_"))
+        if err <= target:
+            hit = {"rtol": rtol, "seconds": rec["seconds"], "iters": rec["iters"], "error": err}
+            break
+    return {"runs": runs, "to_target": hit, "target_error": target}
+
+
+def timed_solve(sem, m, p, b, x, opts, gmres_K=0):
+    """One solve timed from the call to its return (inputs resident)."""
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    if gmres_K:
+        info = sem.sem_gmres_solve(m.h, p.h, gmres_K, b, x, opts)
+    else:
+        info = sem.sem_pcg_solve(m.h, p.h if p is not None else None, b, x, opts)
+    torch.cuda.synchronize()
+    return {"seconds": time.perf_counter() - t, "iters": info["iters"], "relres": info["relres"],
+            "relres_true": info["relres_true"], "coarse_iters": info["coarse_iters"]}
+
+
+def reference_solution(sem, m, b, samples):
+    """FlexCG preconditioned by pMG with FP64 smoothing, to relative residual
+    1e-12: the full-vector reference for solution errors (its own error
+    against the oracle's x* at the sampled DOFs is reported with it)."""
+    import torch
+    pr = sem.Pmg(m, smoother_dtype="f64")
+    xref = torch.empty_like(b)
+    rec = timed_solve(sem, m, pr, b, xref, sem.solve_opts(rtol=1e-12, maxit=200))
+    pr.close()
+    rec["solver"] = "FP64 FlexCG + pMG with FP64 smoothing, rtol 1e-12"
+    rec.update(solution_errors(xref, samples, None))
+    return xref, rec
+
+
+def solve_pair(sem, bm, m, label, skip_pcg=False, samples=None, smoothers=True, rtols=(1e-8, 1e-9, 1e-10, 1e-11)):
+    """FP32-pMG FlexCG (and GMRES(6), Schwarz smoothers) vs FP64 Jacobi-PCG on
+    one mesh: times at rtol 1e-8, then the time each solver needs for a
+    solution error <= 1e-8 (rtol lowered by decades until it holds), errors
+    taken against the sampled oracle x* (if given) and a full FP64 reference."""
     import torch
     from paper_2110_01716_amd import workloads as wl
     out = {}
@@ -111,49 +229,50 @@ def solve_pair(sem, bm, m, label, skip_pcg=False):
     t = time.time()
     p = sem.Pmg(m)
     out["pmg_setup_s"] = time.time() - t
-    info = sem.sem_pcg_solve(m.h, p.h, b, x, sem.solve_opts(rtol=1e-8))  # warm
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    info = sem.sem_pcg_solve(m.h, p.h, b, x, sem.solve_opts(rtol=1e-8))
-    torch.cuda.synchronize()
-    out["pmg_fp32"] = {"seconds": time.perf_counter() - t, "iters": info["iters"], "relres": info["relres"],
-                       "relres_true": info["relres_true"], "coarse_iters": info["coarse_iters"]}
-    log(label, "pmg", out["pmg_fp32"])
-    sem.sem_gmres_solve(m.h, p.h, 6, b, x, sem.solve_opts(rtol=1e-8))  # warm
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    info = sem.sem_gmres_solve(m.h, p.h, 6, b, x, sem.solve_opts(rtol=1e-8))
-    torch.cuda.synchronize()
-    out["pmg_fp32_gmres6"] = {"seconds": time.perf_counter() - t, "iters": info["iters"], "relres": info["relres"],
-                              "relres_true": info["relres_true"], "coarse_iters": info["coarse_iters"]}
-    log(label, "pmg-gmres6", out["pmg_fp32_gmres6"])
-    for sm in ("asm", "ras"):
-        t = time.time()
-        ps = sem.Pmg(m, smoother=sm)
-        setup_s = time.time() - t
-        sem.sem_pcg_solve(m.h, ps.h, b, x, sem.solve_opts(rtol=1e-8))  # warm
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        info = sem.sem_pcg_solve(m.h, ps.h, b, x, sem.solve_opts(rtol=1e-8))
-        torch.cuda.synchronize()
-        out[f"pmg_fp32_cheb_{sm}"] = {"seconds": time.perf_counter() - t, "iters": info["iters"],
-                                      "relres_true": info["relres_true"], "coarse_iters": info["coarse_iters"],
-                                      "setup_s": round(setup_s, 2), "rho": ps.info()["rho"][:2]}
-        log(label, f"pmg-{sm}", out[f"pmg_fp32_cheb_{sm}"])
-        ps.close()
-    if skip_pcg:
-        p.close()
-        return out
+    o8 = sem.solve_opts(rtol=1e-8)
+    sem.sem_pcg_solve(m.h, p.h, b, x, o8)  # warm
+    out["pmg_fp32"] = timed_solve(sem, m, p, b, x, o8)
     xp = x.clone()
-    t = time.perf_counter()
-    info = sem.sem_pcg_solve(m.h, None, b, x, sem.solve_opts(rtol=1e-8, maxit=20000))
-    torch.cuda.synchronize()
-    out["pcg_fp64"] = {"seconds": time.perf_counter() - t, "iters": info["iters"], "relres": info["relres"],
-                       "relres_true": info["relres_true"]}
-    log(label, "pcg", out["pcg_fp64"])
-    out["speedup_pmg_vs_pcg"] = out["pcg_fp64"]["seconds"] / out["pmg_fp32"]["seconds"]
-    out["rel_diff_pmg_vs_pcg"] = float((xp - x).abs().max() / x.abs().max())
+    log(label, "pmg", out["pmg_fp32"])
+    if smoothers:
+        sem.sem_gmres_solve(m.h, p.h, 6, b, x, o8)  # warm
+        out["pmg_fp32_gmres6"] = timed_solve(sem, m, p, b, x, o8, gmres_K=6)
+        log(label, "pmg-gmres6", out["pmg_fp32_gmres6"])
+        for sm in ("asm", "ras"):
+            t = time.time()
+            ps = sem.Pmg(m, smoother=sm)
+            setup_s = time.time() - t
+            sem.sem_pcg_solve(m.h, ps.h, b, x, o8)  # warm
+            rec = timed_solve(sem, m, ps, b, x, o8)
+            rec.update({"setup_s": round(setup_s, 2), "rho": ps.info()["rho"][:2]})
+            out[f"pmg_fp32_cheb_{sm}"] = rec
+            log(label, f"pmg-{sm}", rec)
+            ps.close()
+    xref, out["reference"] = reference_solution(sem, m, b, samples)
+    log(label, "reference", out["reference"])
+    out["pmg_fp32"].update(solution_errors(xp, samples, xref))
+    if samples is not None:
+        out["oracle_samples"] = {"file": samples["file"], "count": int(len(samples["idx"])),
+                                 "oracle_iters": int(samples["meta"].get("iters", 0)),
+                                 "oracle_relres_true": samples["meta"].get("relres_true")}
+    tte = {"pmg_fp32": time_to_error(sem, m, p, b, x, samples, xref, rtols)}
+    log(label, "pmg time-to-error", tte["pmg_fp32"])
+    if not skip_pcg:
+        xw = torch.empty_like(b)
+        sem.sem_pcg_solve(m.h, None, b, xw, sem.solve_opts(maxit=3), check=False)  # workspace
+        tte["pcg_fp64"] = time_to_error(sem, m, None, b, xw, samples, xref, rtols, maxit=50000)
+        log(label, "pcg time-to-error", tte["pcg_fp64"])
+        r0 = tte["pcg_fp64"]["runs"][0]
+        out["pcg_fp64"] = {k: r0[k] for k in ("seconds", "iters", "relres_true") if k in r0}
+        out["pcg_fp64"].update({k: v for k, v in r0.items() if k.startswith("err_")})
+        out["speedup_pmg_vs_pcg"] = out["pcg_fp64"]["seconds"] / out["pmg_fp32"]["seconds"]
+        if tte["pmg_fp32"]["to_target"] and tte["pcg_fp64"]["to_target"]:
+            tte["speedup_pmg_vs_pcg_at_equal_error"] = round(
+                tte["pcg_fp64"]["to_target"]["seconds"] / tte["pmg_fp32"]["to_target"]["seconds"], 2)
+        del xw
+    out["time_to_1e-8_solution_error"] = tte
     p.close()
+    del xref, xp
     return out
 
 
@@ -309,36 +428,93 @@ def bench_serving(sem, rates=(10, 20, 50, 100, 200, 500), window_s=2.0, max_slot
     return out
 
 
-def cpu_baseline(bm_spec, budget_s=12.0):
-    """Oracle Ax (FP64 NumPy) on a bounded sample of the workload, 1 thread."""
+def _oracle_ax_worker(args):
+    """One host core: the oracle's Ax on an n^3-element sample mesh, repeated
+    for `budget` seconds with one BLAS thread. Returns (E, N, seconds per Ax)."""
+    n, N, deform, seed, budget = args
     from threadpoolctl import threadpool_limits
     from oracle import operators as ops
     from paper_2110_01716_amd import workloads as wl
-    n = 16
-    bm = wl.box_mesh(n, N=bm_spec["N"], deform=bm_spec["deform"], seed=bm_spec["seed"])
+    bm = wl.box_mesh(n, N=N, deform=deform, seed=seed)
     with threadpool_limits(limits=1):
         G, _, _ = ops.geometric_factors(bm.N, bm.x, bm.y, bm.z)
         u = np.random.default_rng(0).uniform(-1, 1, bm.x.shape)
         reps, t0 = 0, time.perf_counter()
-        while time.perf_counter() - t0 < budget_s:
+        while time.perf_counter() - t0 < budget:
             ops.ax_local(bm.N, G, u)
             reps += 1
         dt = (time.perf_counter() - t0) / reps
-    return {"value": bm.E * bm.N ** 3 / dt / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 NumPy oracle Ax on a {n}^3-element N={bm.N} deformed box "
-                      f"(same construction as the workload), {reps} repetitions, one thread"}
+    return bm.E, bm.N, dt
 
 
-def oracle_timings():
-    """Host timings of the FP64 oracle (all host cores for BLAS, NumPy
-    pointwise single-threaded): Ax per point, the tiny manufactured problem
-    solved directly and by Jacobi-PCG, and the oracle's pMG-FlexCG on an
-    8^3-element N=7 box, extrapolated per DOF and iteration to the 48^3 case."""
+def cpu_baseline(bm_spec, budget_s=8.0):
+    """The FP64 NumPy oracle on the host cores: its Ax run by one process per
+    core (affinity mask) on a 16^3-element sample of the workload's mesh
+    construction, summed over cores; plus the oracle's solves on the tiny
+    manufactured problem (direct and Jacobi-PCG) and its pMG-FlexCG on an
+    8^3-element box, with the 48^3 figure that follows per element-iteration."""
+    import multiprocessing as mp
+    cores = len(os.sched_getaffinity(0))
+    n = 16
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_ax_worker, [(n, bm_spec["N"], bm_spec["deform"], bm_spec["seed"], budget_s)] * cores)
+    wall = time.perf_counter() - t0
+    value = sum(E * N ** 3 / dt for E, N, dt in res) / 1e9
+    out = {"value": value, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
+           "sample": f"FP64 NumPy oracle Ax on a {n}^3-element N={bm_spec['N']} deformed box (same construction as "
+                     f"the workload), one process per core on {cores} cores, one BLAS thread each, "
+                     f"{budget_s:.0f} s of repetitions per core, rates summed",
+           "host_cpu_count": os.cpu_count(), "affinity_cores": cores, "ax_wall_s": round(wall, 1),
+           "ax_ms_per_core": round(float(np.mean([dt for _, _, dt in res])) * 1e3, 2)}
+    out["solves"] = oracle_solves()
+    return out
+
+
+def oracle_solves():
+    """Oracle solves on the host (BLAS threads on all cores): the tiny
+    manufactured problem by assembly + sparse direct solve and by Jacobi-PCG
+    to 1e-8, and pMG-FlexCG to 1e-8 on an 8^3-element N=7 deformed box."""
     import scipy.sparse.linalg as spla
     from oracle import operators as ops, pmg as opmg, solvers as osv
     from paper_2110_01716_amd import workloads as wl
+    out = {}
+    bm = wl.box_mesh(4, N=7)
+    G, B, _ = ops.geometric_factors(7, bm.x, bm.y, bm.z)
+    b = ops.assemble_rhs(7, B, bm.gid, bm.dirichlet, wl.manufactured_source(bm))
+    t0 = time.perf_counter()
+    A, ids, _ = ops.assemble(7, G, bm.gid, bm.dirichlet)
+    idsall, bu = ops.to_unique(bm.gid, b)
+    spla.spsolve(A.tocsc(), bu[np.searchsorted(idsall, ids)])
+    out["tiny_4^3_N7_direct_s"] = round(time.perf_counter() - t0, 3)
+    dinv = ops.jacobi_inverse(7, G, bm.gid, bm.dirichlet)
+    t0 = time.perf_counter()
+    res = osv.pcg(lambda v: ops.apply_A(7, G, bm.gid, bm.dirichlet, v), lambda r: dinv * r,
+                  lambda x, y: ops.dot(bm.gid, x, y), b, rtol=1e-8)
+    out["tiny_4^3_N7_jacobi_pcg_s"] = round(time.perf_counter() - t0, 3)
+    out["tiny_4^3_N7_jacobi_pcg_iters"] = res.iters
+    bm = wl.box_mesh(8, N=7, deform=0.05, seed=1002)
+    t0 = time.perf_counter()
+    lv = opmg.build_levels(7, bm.x, bm.y, bm.z, bm.gid, bm.dirichlet)
+    out["pmg_8^3_N7_setup_s"] = round(time.perf_counter() - t0, 2)
+    b = wl.random_rhs(bm, 2000)
+    t0 = time.perf_counter()
+    res = opmg.pmg_flexcg(lv, b, opmg.VCycleOpts(), rtol=1e-8)
+    solve = time.perf_counter() - t0
+    out["pmg_8^3_N7_solve_s"] = round(solve, 2)
+    out["pmg_8^3_N7_iters"] = res.iters
+    out["pmg_48^3_N7_extrapolated_s"] = round(solve / max(res.iters, 1) / bm.E * 48 ** 3 * 13, 1)
+    out["note"] = ("48^3 figure extrapolated per element-iteration at 13 iterations; the measured 48^3 oracle "
+                   "solve (build host) is in the header of the sampled-solution file")
+    return out
+
+
+def oracle_timings():
+    """Host timings of the FP64 oracle only (no GPU): its Ax with BLAS on all
+    host cores, and the oracle solves of cpu_baseline."""
+    from oracle import operators as ops
+    from paper_2110_01716_amd import workloads as wl
     out = {"cores": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
-    # Ax
     for n in (4, 16):
         bm = wl.box_mesh(n, N=7, deform=0.05 if n > 4 else 0.0, seed=1000 + n)
         G, _, _ = ops.geometric_factors(7, bm.x, bm.y, bm.z)
@@ -350,36 +526,7 @@ def oracle_timings():
         dt = (time.perf_counter() - t0) / reps
         out[f"ax_{n}^3_N7_ms"] = round(dt * 1e3, 3)
         out[f"ax_{n}^3_N7_gdofs"] = round(bm.E * 343 / dt / 1e9, 4)
-    # tiny manufactured problem: direct and Jacobi-PCG
-    bm = wl.box_mesh(4, N=7)
-    G, B, _ = ops.geometric_factors(7, bm.x, bm.y, bm.z)
-    b = ops.assemble_rhs(7, B, bm.gid, bm.dirichlet, wl.manufactured_source(bm))
-    t0 = time.perf_counter()
-    A, ids, _ = ops.assemble(7, G, bm.gid, bm.dirichlet)
-    idsall, bu = ops.to_unique(bm.gid, b)
-    spla.spsolve(A.tocsc(), bu[np.searchsorted(idsall, ids)])
-    out["tiny_direct_s"] = round(time.perf_counter() - t0, 3)
-    dinv = ops.jacobi_inverse(7, G, bm.gid, bm.dirichlet)
-    t0 = time.perf_counter()
-    res = osv.pcg(lambda v: ops.apply_A(7, G, bm.gid, bm.dirichlet, v), lambda r: dinv * r,
-                  lambda x, y: ops.dot(bm.gid, x, y), b, rtol=1e-8)
-    out["tiny_jacobi_pcg_s"] = round(time.perf_counter() - t0, 3)
-    out["tiny_jacobi_pcg_iters"] = res.iters
-    # pMG FlexCG on 8^3, extrapolated per DOF-iteration to 48^3 (13 iterations measured on the GPU)
-    bm = wl.box_mesh(8, N=7, deform=0.05, seed=1002)
-    t0 = time.perf_counter()
-    lv = opmg.build_levels(7, bm.x, bm.y, bm.z, bm.gid, bm.dirichlet)
-    setup = time.perf_counter() - t0
-    b = wl.random_rhs(bm, 2000)
-    t0 = time.perf_counter()
-    res = opmg.pmg_flexcg(lv, b, opmg.VCycleOpts(), rtol=1e-8)
-    solve = time.perf_counter() - t0
-    per = solve / max(res.iters, 1) / bm.E
-    out["pmg_8^3_N7_setup_s"] = round(setup, 2)
-    out["pmg_8^3_N7_solve_s"] = round(solve, 2)
-    out["pmg_8^3_N7_iters"] = res.iters
-    out["pmg_48^3_N7_extrapolated_s"] = round(per * 48 ** 3 * 13, 1)
-    out["note"] = "48^3 figure extrapolated from the 8^3 run per element-iteration at 13 iterations"
+    out.update(oracle_solves())
     return out
 
 
@@ -389,7 +536,7 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--solve-c2", action="store_true")
+    ap.add_argument("--no-c2-solve", action="store_true", help="skip the 64^3 Jacobi-PCG / pMG solves")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--skip-pcg", action="store_true", help="time only the pMG solve")
@@ -456,7 +603,9 @@ def main():
     if a.solve_only:
         spec3 = wl.config_meshes()["pmg_48x48x48_N7"]
         bm3, m3 = build_mesh(sem, spec3)
-        print(json.dumps({"poisson": {"48x48x48_N7": solve_pair(sem, bm3, m3, "c3", a.skip_pcg)}}), flush=True)
+        print(json.dumps({"poisson": {"48x48x48_N7": solve_pair(sem, bm3, m3, "c3", a.skip_pcg,
+                                                                samples=load_xstar_samples(spec3["n"]))}}),
+              flush=True)
         return
     bm, m = build_mesh(sem, spec)
     E, N = bm.E, bm.N
@@ -500,15 +649,25 @@ def main():
                            "hbm_gbs": round(hgbs, 1), "frac": round(hgbs / HBM_PEAK_GBS, 4), "bytes_per_point": 72,
                            "kernel": "k_ax<7,double,helmholtz>"}
     log("helmholtz ax", res["helmholtz_ax"])
+    st = time_stream(sem, E * Np, a.steps, a.warmup)
+    log("stream", st)
+    rl = res["roofline"]
+    rl["realizable"] = {"probe": "sem_stream (k_stream<n_in>), FP64, %d elements per array" % st["elements"],
+                        "copy_GBs": st["copy"]["GBs"], "triad_GBs": st["triad"]["GBs"],
+                        "ax_mix_7r1w_GBs": st["ax_mix_7r1w"]["GBs"],
+                        "triad_frac_of_peak": round(st["triad"]["GBs"] / HBM_PEAK_GBS, 4),
+                        "ax_frac_of_triad": round(gbs / st["triad"]["GBs"], 4),
+                        "ax_frac_of_mix": round(gbs / st["ax_mix_7r1w"]["GBs"], 4)}
     if not a.no_solve:
         poisson = {}
-        if a.solve_c2:
-            poisson["64x64x64_N7"] = solve_pair(sem, bm, m, "c2")
+        if not a.no_c2_solve:
+            # config 2: FP64 Jacobi-PCG to 1e-8 on the Ax mesh, beside the FP32-pMG solve
+            poisson["64x64x64_N7"] = solve_pair(sem, bm, m, "c2", samples=None, smoothers=False, rtols=(1e-8,))
         m.close()
         del bm
         spec3 = wl.config_meshes()["pmg_48x48x48_N7"]
         bm3, m3 = build_mesh(sem, spec3)
-        poisson["48x48x48_N7"] = solve_pair(sem, bm3, m3, "c3", a.skip_pcg)
+        poisson["48x48x48_N7"] = solve_pair(sem, bm3, m3, "c3", a.skip_pcg, samples=load_xstar_samples(spec3["n"]))
         poisson["48x48x48_N7"]["helmholtz_jacobi_pcg"] = bench_helmholtz_solve(sem, bm3, m3)
         if not a.no_projection:
             poisson["48x48x48_N7"]["projection"] = bench_projection(sem, bm3, m3)

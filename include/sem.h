@@ -351,6 +351,20 @@ int sem_batch_release(sem_batch b, int slot);
 
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* Bandwidth probe (Performance Measurements: each kernel is rated against   */
+/* the realizable memory bandwidth that a STREAM triad reaches, and counts   */
+/* as roofline performance above 70% of it)                                 */
+/* ------------------------------------------------------------------------ */
+
+/* dst[i] = src[0][i] + s * sum_{k=1}^{n_in-1} src[k][i] for 0 <= i < n.
+ * src: device, n_in contiguous arrays of n doubles ([n_in][n]); dst: device,
+ * n doubles; both caller-owned, 16-byte aligned, not overlapping. n_in = 1 is
+ * a copy, n_in = 2 the STREAM triad a = b + s c, n_in = 7 the FP64 local
+ * Laplacian's read:write mix (seven streams in, one out). 1 <= n_in <= 8, n
+ * even and >= 0 (n = 0 does nothing); otherwise SEM_EINVAL. Asynchronous. */
+int sem_stream(int n_in, const double* src, double* dst, double s, int64_t n, void* stream);
+
 const char* sem_status_string(int status);
 const char* sem_last_error(void);
 

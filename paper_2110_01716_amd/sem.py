@@ -112,6 +112,7 @@ _SIGS = {
     "sem_proj_set_gmres": (C.c_int, [_P, C.c_int]),
     "sem_proj_export": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "sem_pcg_solve_projected": (C.c_int, [_P, _P, _P, _P, C.POINTER(sem_solve_opts), C.POINTER(sem_solve_info), _P]),
+    "sem_stream": (C.c_int, [C.c_int, _P, _P, C.c_double, C.c_int64, _P]),
     "sem_status_string": (C.c_char_p, [C.c_int]),
     "sem_last_error": (C.c_char_p, []),
 }
@@ -246,6 +247,12 @@ def sem_dot(h, a, b, stream=None) -> float:
     r = C.c_double()
     _check(load().sem_dot(h, _dtype_code(a), _ptr(a), _ptr(b), C.byref(r), _stream(stream)), "sem_dot")
     return r.value
+
+
+def sem_stream(n_in, src, dst, s=1.0, n=None, stream=None):
+    """dst = src[0] + s * (src[1] + ... + src[n_in-1]); src is a [n_in, n] FP64 tensor."""
+    n = dst.numel() if n is None else n
+    _check(load().sem_stream(n_in, _ptr(src), _ptr(dst), s, n, _stream(stream)), "sem_stream")
 
 
 def pmg_opts(**kw) -> sem_pmg_opts:

@@ -68,3 +68,8 @@ def test_host_argument_errors(lib):
     assert b"outside" in lib.sem_last_error()
     assert lib.sem_mesh_create(None, None) == sem.SEM_EINVAL
     assert lib.sem_status_string(sem.SEM_ENOCONV).startswith(b"SEM_ENOCONV")
+    # bandwidth probe: argument checks happen before any device work
+    assert lib.sem_stream(0, None, None, 1.0, 2, None) == sem.SEM_EINVAL
+    assert lib.sem_stream(9, None, None, 1.0, 2, None) == sem.SEM_EINVAL
+    assert lib.sem_stream(2, None, None, 1.0, 3, None) == sem.SEM_EINVAL
+    assert lib.sem_stream(2, None, None, 1.0, 0, None) == sem.SEM_OK

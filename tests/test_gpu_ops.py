@@ -179,3 +179,23 @@ def test_mesh_errors(sem):
     with pytest.raises(sem.SemError) as ei:
         sem.Mesh(3, bm.x, bm.y, bm.z, g, bm.dirichlet)
     assert ei.value.code == sem.SEM_EINVAL
+
+
+@pytest.mark.parametrize("n_in", [1, 2, 7, 8])
+def test_stream_probe(sem, n_in):
+    """The bandwidth probe computes dst = src0 + s (src1 + ... ) exactly as
+    written (sums of up to eight terms in index order)."""
+    import torch
+    print_case("stream", n_in)
+    n = 3 * 512 + 6  # a ragged last block
+    rng = np.random.default_rng(n_in)
+    src = rng.uniform(-1, 1, (n_in, n))
+    dst = torch.empty(n, dtype=torch.float64, device="cuda")
+    sem.sem_stream(n_in, dev(src), dst, 0.5)  # a power of two: the product is exact, fused or not
+    exp = src[0].copy()
+    if n_in > 1:
+        t = src[1].copy()
+        for k in range(2, n_in):
+            t = t + src[k]
+        exp = exp + 0.5 * t
+    assert np.array_equal(host(dst), exp)

@@ -57,9 +57,16 @@ def test_jacobi_pcg_tiny_manufactured(sem):
     bo = ops.assemble_rhs(7, B, bm.gid, bm.dirichlet, wl.manufactured_source(bm))
     xs = direct_solution(bm, bo)
     xg = host(x)
-    assert rel_err(xg, xs) <= 1e-7
+    err_1e8 = rel_err(xg, xs)
+    assert err_1e8 <= 1e-7
     # spectral accuracy of the discrete solution itself
     assert np.max(np.abs(xg - wl.manufactured_solution(bm))) < 1e-5
+    # the solution itself to 1e-8 relative against the oracle's direct solve
+    info = sem.sem_pcg_solve(m.h, None, b, x, sem.solve_opts(rtol=1e-10))
+    assert info["status"] == 0 and info["relres_true"] <= 2e-10
+    err = rel_err(host(x), xs)
+    print(f"tiny manufactured: error {err_1e8:.2e} at rtol 1e-8, {err:.2e} at rtol 1e-10", flush=True)
+    assert err <= 1e-8
 
 
 def test_jacobi_pcg_matches_oracle_iterates(sem):
@@ -103,14 +110,20 @@ def _levels_oracle(bm, rho=None):
     return opmg.build_levels(bm.N, bm.x, bm.y, bm.z, bm.gid, bm.dirichlet, rho=rho)
 
 
-def test_pmg_hierarchy_matches_oracle(sem):
+HIERARCHIES = {5: [5, 2, 1], 7: [7, 3, 1], 9: [9, 4, 1]}
+
+
+@pytest.mark.parametrize("N", [5, 7, 9])
+def test_pmg_hierarchy_matches_oracle(sem, N):
     import torch
-    print_case("pmg-hierarchy")
-    bm = wl.box_mesh(3, 2, 2, N=7, deform=0.05, seed=6)
+    from oracle import solvers
+    from oracle.counter_rng import start_vector
+    print_case("pmg-hierarchy", N)
+    bm = wl.box_mesh(3, 2, 2, N=N, deform=0.05, seed=6)
     m = sem.Mesh.from_box(bm)
     p = sem.Pmg(m)
     info = p.info()
-    assert info["orders"] == [7, 3, 1]
+    assert info["orders"] == HIERARCHIES[N]
     lv = _levels_oracle(bm)
     # fine-level rho from the same splitmix64 start vector
     assert abs(info["rho"][0] - lv[0].rho) <= 1e-10 * lv[0].rho
@@ -136,6 +149,12 @@ def test_pmg_hierarchy_matches_oracle(sem):
         assert rel_err(host(G), o.G) <= 1e-12
         assert rel_err(host(D), o.dinv) <= 1e-12
         del n
+        if l == 1:
+            # smoothed coarse level: the oracle's power iteration on its own
+            # operator, started from the splitmix64 vector of the GPU's coarse IDs
+            v0 = ops.mask(o.dirichlet, start_vector(g))
+            rho_o = solvers.power_rho(o.A, o.dinv, o.dot, v0, iters=20)
+            assert abs(info["rho"][1] - rho_o) <= 1e-9 * rho_o
 
 
 def test_pmg_coarse_ids_on_relabelled_mesh(sem):
@@ -149,11 +168,12 @@ def test_pmg_coarse_ids_on_relabelled_mesh(sem):
     assert info["n_unique"][2] == 3 * 4 * 3
 
 
+@pytest.mark.parametrize("N", [5, 7, 9])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_transfers_match_oracle(sem, dtype):
+def test_transfers_match_oracle(sem, dtype, N):
     import torch
-    print_case("transfers", dtype)
-    bm = wl.box_mesh(2, 3, 2, N=7, deform=0.05, seed=8)
+    print_case("transfers", dtype, N)
+    bm = wl.box_mesh(2, 3, 2, N=N, deform=0.05, seed=8)
     m = sem.Mesh.from_box(bm)
     p = sem.Pmg(m, smoother_dtype=dtype, rho_override=[2.0, 2.0])
     lv = _levels_oracle(bm, rho=[2.0, 2.0])
@@ -174,9 +194,9 @@ def test_transfers_match_oracle(sem, dtype):
         assert rel_err(host(xf), base + opmg.prolong(lv, l, zc)) <= tol
 
 
-def _vcycle_case(sem, dtype, coarse_iters=6):
+def _vcycle_case(sem, dtype, coarse_iters=6, N=7):
     import torch
-    bm = wl.box_mesh(3, 2, 3, N=7, deform=0.05, seed=9)
+    bm = wl.box_mesh(3, 2, 3, N=N, deform=0.05, seed=9)
     lv = _levels_oracle(bm)
     rho = [lv[0].rho, lv[1].rho]
     m = sem.Mesh.from_box(bm)
@@ -189,23 +209,25 @@ def _vcycle_case(sem, dtype, coarse_iters=6):
     return host(z), zo
 
 
-def test_vcycle_fp64_matches_oracle(sem):
-    print_case("vcycle-f64")
-    z, zo = _vcycle_case(sem, "f64")
+@pytest.mark.parametrize("N", [5, 7, 9])
+def test_vcycle_fp64_matches_oracle(sem, N):
+    print_case("vcycle-f64", N)
+    z, zo = _vcycle_case(sem, "f64", N=N)
     assert rel_err(z, zo) <= 1e-12
 
 
-def test_vcycle_fp32_matches_oracle(sem):
-    print_case("vcycle-f32")
-    z, zo = _vcycle_case(sem, "f32")
+@pytest.mark.parametrize("N", [5, 7, 9])
+def test_vcycle_fp32_matches_oracle(sem, N):
+    print_case("vcycle-f32", N)
+    z, zo = _vcycle_case(sem, "f32", N=N)
     assert rel_err(z, zo) <= 1e-5
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_pmg_flexcg_solution(sem, dtype):
+@pytest.mark.parametrize("dtype,N", [("f32", 7), ("f64", 7), ("f32", 5), ("f32", 9)])
+def test_pmg_flexcg_solution(sem, dtype, N):
     import torch
-    print_case("flexcg", dtype)
-    bm = wl.box_mesh(3, 3, 2, N=7, deform=0.05, seed=10)
+    print_case("flexcg", dtype, N)
+    bm = wl.box_mesh(3, 3, 2, N=N, deform=0.05, seed=10)
     m = sem.Mesh.from_box(bm)
     p = sem.Pmg(m, smoother_dtype=dtype)
     b = wl.random_rhs(bm, 2)
