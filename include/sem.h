@@ -155,6 +155,17 @@ int sem_mass(sem_mesh m, sem_dtype t, const void* u, void* Bu, void* stream);
  * order). Synchronous. */
 int sem_dot(sem_mesh m, sem_dtype t, const void* a, const void* b, double* result, void* stream);
 
+/* sem_dot for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same product with its partial sums kept in a static device array of the
+ * library (1 MiB per device, held until the process ends) instead of a
+ * buffer allocated per call; the sum of the partials is reduced on the device
+ * in a fixed order, so the result can differ from sem_dot's in the last bits.
+ * Makes no device allocation. The current device must be the mesh's. Limit:
+ * n_local <= 134,217,728 (2^27) local points, else SEM_EINVAL. Calls that
+ * overlap on one device share the array and race. Synchronous. */
+int sem_dot_noalloc(sem_mesh m, sem_dtype t, const void* a, const void* b, double* result, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* p-multigrid (Implementation, pMG paragraph)                               */
 /* ------------------------------------------------------------------------ */

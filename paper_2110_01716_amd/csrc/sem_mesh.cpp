@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "sem_internal.h"
 
@@ -196,10 +197,11 @@ void vec_op1(VecOp op, int64_t n, double* x, const double* r, double c0, const d
   launch_vec<double>(op, t, vec_blocks(n), s);
 }
 
-double mesh_dot(const MeshData& m, sem_dtype t, const void* a, const void* b, hipStream_t s) {
+// per-block partial sums of the unique-DOF product a.b into partial[0, nb)
+// (V_DOT2 also fills partial[nb, 2 nb)), nb = vec_blocks(m.nloc)
+static void dot_partials(const MeshData& m, sem_dtype t, const void* a, const void* b, double* partial,
+                         hipStream_t s) {
   const int64_t nb = vec_blocks(m.nloc);
-  DevBuf part;
-  part.alloc(sizeof(double) * 2 * nb);
   if (t == SEM_F64) {
     Table<VecArgs<double>> tb;
     tb.one.n = m.nloc;
@@ -207,7 +209,7 @@ double mesh_dot(const MeshData& m, sem_dtype t, const void* a, const void* b, hi
     tb.one.w = (double*)b;
     tb.one.r = (double*)b;
     tb.one.owner = m.owner.as<uint8_t>();
-    tb.one.partial = part.as<double>();
+    tb.one.partial = partial;
     tb.one.stride = nb;
     launch_vec<double>(V_DOT2, tb, nb, s);
   } else {
@@ -217,10 +219,17 @@ double mesh_dot(const MeshData& m, sem_dtype t, const void* a, const void* b, hi
     tb.one.w = (float*)b;
     tb.one.r = (float*)b;
     tb.one.owner = m.owner.as<uint8_t>();
-    tb.one.partial = part.as<double>();
+    tb.one.partial = partial;
     tb.one.stride = nb;
     launch_vec<float>(V_DOT2, tb, nb, s);
   }
+}
+
+double mesh_dot(const MeshData& m, sem_dtype t, const void* a, const void* b, hipStream_t s) {
+  const int64_t nb = vec_blocks(m.nloc);
+  DevBuf part;
+  part.alloc(sizeof(double) * 2 * nb);
+  dot_partials(m, t, a, b, part.as<double>(), s);
   std::vector<double> h(nb);
   SEM_HIP(hipMemcpyAsync(h.data(), part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
   SEM_HIP(hipStreamSynchronize(s));
@@ -228,6 +237,41 @@ double mesh_dot(const MeshData& m, sem_dtype t, const void* a, const void* b, hi
   for (int64_t k = 0; k < nb; ++k) sum += h[k];
   return sum;
 }
+
+// ---------------------------------------------------------------------------
+// allocation-free inner product (sem_dot_noalloc)
+//
+// The partial sums live in a file-scope device array instead of a buffer
+// allocated per call. In host code `scratch` only names the symbol: its
+// device address is looked up once per device (hipGetSymbolAddress, with that
+// device current) and only that address is ever handed to kernels or copies.
+// Every slot a call reads is written earlier in the same call (partials, then
+// the reduced result), so nothing needs clearing between calls; calls that
+// overlap on one device share the array and race.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kDotScratchBlocks = 65536;  // partial sums per row: vec_blocks(n_local) <= this
+constexpr int64_t kDotResult = 2 * kDotScratchBlocks;  // slot of the reduced sum
+constexpr int64_t kDotScratchDoubles = kDotResult + 32;  // 1 MiB + 256 B
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kDotScratchDoubles];
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+double* scratch_address() {
+  int dev = 0;
+  SEM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(SEM_EINVAL, "sem_dot_noalloc: device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    SEM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(SEM_EHIP, "sem_dot_noalloc: no device address for the scratch array on device %d", dev);
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // mesh construction
@@ -448,6 +492,27 @@ extern "C" int sem_dot(sem_mesh mh, sem_dtype t, const void* a, const void* b, d
     if (!mh || !a || !b || !result) fail(SEM_EINVAL, "sem_dot: NULL argument");
     check_dtype(t, "sem_dot");
     *result = mesh_dot(mh->d, t, a, b, (hipStream_t)stream);
+  });
+}
+
+extern "C" int sem_dot_noalloc(sem_mesh mh, sem_dtype t, const void* a, const void* b, double* result,
+                               void* stream) {
+  return guarded([&] {
+    if (!mh || !a || !b || !result) fail(SEM_EINVAL, "sem_dot_noalloc: NULL argument");
+    check_dtype(t, "sem_dot_noalloc");
+    const MeshData& m = mh->d;
+    const int64_t nb = vec_blocks(m.nloc);
+    if (nb > kDotScratchBlocks)
+      fail(SEM_EINVAL,
+           "sem_dot_noalloc: %lld local points need %lld partial sums, more than the %lld of the static scratch "
+           "(at most 134217728 local points)",
+           (long long)m.nloc, (long long)nb, (long long)kDotScratchBlocks);
+    hipStream_t s = (hipStream_t)stream;
+    double* part = scratch_address();
+    dot_partials(m, t, a, b, part, s);
+    launch_mfin(part, nb, nb, 1, part + kDotResult, s);
+    SEM_HIP(hipMemcpyAsync(result, part + kDotResult, sizeof(double), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
   });
 }
 

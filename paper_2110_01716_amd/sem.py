@@ -85,6 +85,7 @@ _SIGS = {
     "sem_gs": (C.c_int, [_P, C.c_int, _P, C.c_int, _P]),
     "sem_mass": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "sem_dot": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(C.c_double), _P]),
+    "sem_dot_noalloc": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(C.c_double), _P]),
     "sem_pmg_opts_default": (None, [C.POINTER(sem_pmg_opts)]),
     "sem_pmg_setup": (C.c_int, [_P, C.POINTER(sem_pmg_opts), C.POINTER(_P)]),
     "sem_pmg_destroy": (C.c_int, [_P]),
@@ -253,6 +254,13 @@ def sem_stream(n_in, src, dst, s=1.0, n=None, stream=None):
     """dst = src[0] + s * (src[1] + ... + src[n_in-1]); src is a [n_in, n] FP64 tensor."""
     n = dst.numel() if n is None else n
     _check(load().sem_stream(n_in, _ptr(src), _ptr(dst), s, n, _stream(stream)), "sem_stream")
+
+
+def sem_dot_noalloc(h, a, b, stream=None) -> float:
+    r = C.c_double()
+    _check(load().sem_dot_noalloc(h, _dtype_code(a), _ptr(a), _ptr(b), C.byref(r), _stream(stream)),
+           "sem_dot_noalloc")
+    return r.value
 
 
 def pmg_opts(**kw) -> sem_pmg_opts:

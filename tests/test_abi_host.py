@@ -73,3 +73,4 @@ def test_host_argument_errors(lib):
     assert lib.sem_stream(9, None, None, 1.0, 2, None) == sem.SEM_EINVAL
     assert lib.sem_stream(2, None, None, 1.0, 3, None) == sem.SEM_EINVAL
     assert lib.sem_stream(2, None, None, 1.0, 0, None) == sem.SEM_OK
+    assert lib.sem_dot_noalloc(None, 0, None, None, None, None) == sem.SEM_EINVAL
