@@ -285,6 +285,28 @@ def test_batched_equals_alone_bitwise(sem):
         assert torch.equal(xa, xb)
 
 
+def test_batched_solutions_match_oracle(sem):
+    """The batched configuration's problem mix (N = 5, 7 and 9, hierarchies
+    5->2->1, 7->3->1, 9->4->1, deformed boxes of different sizes) solved in
+    one batched call by FP64 flexible CG + FP32 pMG at rtol 1e-10: every
+    solution within 1e-8 of the oracle's direct solve."""
+    import torch
+    print_case("batched-oracle")
+    specs = [(2, 5, 11), (3, 7, 12), (2, 9, 13), (3, 5, 14), (1, 9, 15), (2, 7, 16)]
+    bms = [wl.box_mesh(n, N=N, deform=0.05, seed=1000 + sd) for n, N, sd in specs]
+    meshes = [sem.Mesh.from_box(bm) for bm in bms]
+    pmgs = [sem.Pmg(m) for m in meshes]
+    bh = [wl.random_rhs(bm, 2000 + k) for k, bm in enumerate(bms)]
+    bs = [dev(b) for b in bh]
+    xs = [torch.empty_like(b) for b in bs]
+    rc, infos = sem.sem_pcg_solve_batched([m.h for m in meshes], [p.h for p in pmgs], bs, xs,
+                                          sem.solve_opts(rtol=1e-10))
+    assert rc == 0
+    for bm, b, x, info in zip(bms, bh, xs, infos):
+        assert info["status"] == 0 and info["relres_true"] <= 1.05e-10
+        assert rel_err(host(x), direct_solution(bm, b)) <= 1e-8, (bm.N, bm.E)
+
+
 def test_continuous_batching_equals_alone(sem):
     import torch
     print_case("continuous")

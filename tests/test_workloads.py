@@ -92,3 +92,31 @@ def test_rotate_elements_keeps_the_mesh():
         assert sorted(m.gid[e]) == sorted(r.gid[e])
         order = np.argsort(r.gid[e])
         assert np.array_equal(r.x[e][order], m.x[e][np.argsort(m.gid[e])])
+
+
+def test_oracle_solution_samples_file():
+    """The stored oracle samples of the 48^3 mixed-precision workload are
+    well formed: 2000 distinct local indices inside the mesh, the oracle's
+    true residual at 1e-12, and max |x*| at least every sampled |x*|."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "pmg_48x48x48_N7_rhs2000_xstar_samples.txt")
+    meta, idx, val = {}, [], []
+    for line in open(path):
+        if line.startswith("#"):
+            parts = line[1:].split()
+            if len(parts) == 2:
+                try:
+                    meta[parts[0]] = float(parts[1])
+                except ValueError:
+                    pass
+            continue
+        i, v = line.split()
+        idx.append(int(i))
+        val.append(float(v))
+    idx = np.array(idx)
+    assert len(idx) == int(meta["samples"]) == 2000
+    assert np.all(np.diff(idx) > 0) and idx[0] >= 0 and idx[-1] < 48 ** 3 * 512
+    assert meta["relres_true"] <= 1e-12
+    assert int(meta["n_unique"]) == (48 * 7 + 1) ** 3
+    assert np.max(np.abs(val)) <= meta["xstar_max_abs"]
