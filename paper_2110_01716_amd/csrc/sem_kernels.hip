@@ -356,6 +356,58 @@ int64_t vec_blocks(int64_t n) {
   return (n + chunk - 1) / chunk;
 }
 
+// operands each vector op reads (bit mask), so all of a thread's loads are
+// issued before any of its stores
+enum : unsigned {
+  RD_X = 1, RD_R = 2, RD_P = 4, RD_W = 8, RD_Z = 16, RD_T = 32, RD_RES = 64, RD_D = 128, RD_DINV = 256,
+  RD_IN64 = 512, RD_W64 = 1024, RD_OWN = 2048
+};
+constexpr unsigned vec_reads(int op) {
+  switch (op) {
+    case V_PCG_UPDATE: return RD_X | RD_P | RD_R | RD_W | RD_OWN | RD_DINV;
+    case V_P_JACOBI: return RD_DINV | RD_R | RD_P;
+    case V_P_FLEX: return RD_Z | RD_P;
+    case V_DOT2: return RD_OWN | RD_Z | RD_W | RD_R;
+    case V_DOT1: return RD_OWN | RD_R;
+    case V_RZ_JACOBI: return RD_DINV | RD_R | RD_OWN;
+    case V_CHEB_INIT0: return RD_DINV | RD_R;
+    case V_CHEB_INITX: return RD_R | RD_T | RD_DINV | RD_X;
+    case V_CHEB_STEP0: return RD_R | RD_T | RD_D | RD_DINV | RD_X;
+    case V_CHEB_STEP: return RD_RES | RD_T | RD_D | RD_DINV | RD_X;
+    case V_CHEB_INIT0D: return RD_DINV | RD_R;
+    case V_CHEB_INIT0D_IN64: return RD_IN64 | RD_DINV;
+    case V_CHEB_STEP0X: return RD_R | RD_T | RD_D | RD_DINV;
+    case V_CHEB_LAST0X: return RD_D | RD_DINV | RD_R | RD_T;
+    case V_CHEB_LAST: return RD_X | RD_D | RD_DINV | RD_RES | RD_T;
+    case V_CHEB_LAST_OUT64: return RD_X | RD_D | RD_DINV | RD_RES | RD_T | RD_OWN | RD_W64 | RD_IN64;
+    case V_CHEB_INITX_LAST: return RD_X | RD_DINV | RD_R | RD_T;
+    case V_CHEB_INITX_OUT64: return RD_X | RD_DINV | RD_R | RD_T | RD_OWN | RD_W64 | RD_IN64;
+    case V_RES0: return RD_R | RD_T;
+    case V_RES: return RD_RES | RD_T;
+    case V_CHEB_UPD: return RD_D | RD_DINV | RD_R | RD_X;
+    case V_CHEB_UPD0: return RD_DINV | RD_R | RD_X;
+    case V_CHEB_UPD_OUT64: return RD_D | RD_DINV | RD_R | RD_X | RD_OWN | RD_W64 | RD_IN64;
+    case V_CHEB_UPD0_OUT64: return RD_DINV | RD_R | RD_X | RD_OWN | RD_W64 | RD_IN64;
+    case V_COPY: return RD_R;
+    case V_SCALE_DINV: return RD_DINV | RD_R;
+    case V_NORMALIZE: return RD_R;
+    case V_TRUE_RES: return RD_OWN | RD_R | RD_T;
+    case V_DIV_DINV: return RD_DINV | RD_R;
+    case V_SCALE: return RD_R;
+    case V_AXPY: return RD_X | RD_R;
+    default: return 0;  // V_ZERO, V_FILL
+  }
+}
+
+template <typename P>
+__device__ __forceinline__ P vld(const SEM_GLOBAL P* a, int64_t l) {
+  return __builtin_nontemporal_load(a + l);
+}
+template <typename P>
+__device__ __forceinline__ void vst(SEM_GLOBAL P* a, int64_t l, P v) {
+  __builtin_nontemporal_store(v, a + l);
+}
+
 template <typename T, int OP>
 __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
   __shared__ double s_red[2][kVecThreads / 64];
@@ -380,133 +432,158 @@ __global__ __launch_bounds__(kVecThreads) void k_vec(Table<VecArgs<T>> tab) {
   if constexpr (OP == V_P_JACOBI || OP == V_P_FLEX) beta = (T)gl(a.scal)[S_BETA];
   if constexpr (OP == V_NORMALIZE) scale = (T)gl(a.scal)[S_TMP];
   const T c0 = (T)a.c0, c1 = (T)a.c1, c2 = (T)a.c2;
+  constexpr unsigned RD = vec_reads(OP);
+  // every point a thread owns touches only its own index, so all loads may
+  // go first even where two of the vectors alias (in-place updates)
+  T xv[kVecPer], rv[kVecPer], pv[kVecPer], wv[kVecPer], zv[kVecPer], tv[kVecPer], resv[kVecPer], dv[kVecPer],
+      dinvv[kVecPer];
+  double in64v[kVecPer], w64v[kVecPer];
+  bool own[kVecPer], ok[kVecPer];
 #pragma unroll
   for (int q = 0; q < kVecPer; ++q) {
     const int64_t l = base + (int64_t)q * kVecThreads;
-    if (q >= per || l >= a.n) break;
+    ok[q] = q < per && l < a.n;
+    if (!ok[q]) continue;
+    if constexpr ((RD & RD_X) != 0) xv[q] = vld(X, l);
+    if constexpr ((RD & RD_R) != 0) rv[q] = vld(R, l);
+    if constexpr ((RD & RD_P) != 0) pv[q] = vld(P, l);
+    if constexpr ((RD & RD_W) != 0) wv[q] = vld(W, l);
+    if constexpr ((RD & RD_Z) != 0) zv[q] = vld(Z, l);
+    if constexpr ((RD & RD_T) != 0) tv[q] = vld(Tt, l);
+    if constexpr ((RD & RD_RES) != 0) resv[q] = vld(RES, l);
+    if constexpr ((RD & RD_D) != 0) dv[q] = vld(Dd, l);
+    if constexpr ((RD & RD_DINV) != 0) dinvv[q] = DINV ? vld(DINV, l) : T(0);
+    if constexpr ((RD & RD_IN64) != 0) in64v[q] = vld(gl(a.in64), l);
+    if constexpr ((RD & RD_W64) != 0) w64v[q] = vld(gl(a.w64), l);
+    if constexpr ((RD & RD_OWN) != 0) own[q] = !OWN || vld(OWN, l);
+  }
+#pragma unroll
+  for (int q = 0; q < kVecPer; ++q) {
+    if (!ok[q]) continue;
+    const int64_t l = base + (int64_t)q * kVecThreads;
     if constexpr (OP == V_PCG_UPDATE) {
-      X[l] += alpha * P[l];
-      const T rn = R[l] - alpha * W[l];
-      R[l] = rn;
-      if (!OWN || OWN[l]) {
+      vst(X, l, xv[q] + alpha * pv[q]);
+      const T rn = rv[q] - alpha * wv[q];
+      vst(R, l, rn);
+      if (own[q]) {
         acc0 += (double)rn * (double)rn;
-        if (DINV) acc1 += (double)rn * (double)DINV[l] * (double)rn;
+        if (DINV) acc1 += (double)rn * (double)dinvv[q] * (double)rn;
       }
     } else if constexpr (OP == V_P_JACOBI) {
-      P[l] = DINV[l] * R[l] + beta * P[l];
+      vst(P, l, dinvv[q] * rv[q] + beta * pv[q]);
     } else if constexpr (OP == V_P_FLEX) {
-      P[l] = Z[l] + beta * P[l];
+      vst(P, l, zv[q] + beta * pv[q]);
     } else if constexpr (OP == V_DOT2) {
-      if (!OWN || OWN[l]) {
-        const double zl = (double)Z[l];
-        acc0 += zl * (double)W[l];
-        acc1 += zl * (double)R[l];
+      if (own[q]) {
+        const double zl = (double)zv[q];
+        acc0 += zl * (double)wv[q];
+        acc1 += zl * (double)rv[q];
       }
     } else if constexpr (OP == V_DOT1) {
-      if (!OWN || OWN[l]) acc0 += (double)R[l] * (double)R[l];
+      if (own[q]) acc0 += (double)rv[q] * (double)rv[q];
     } else if constexpr (OP == V_RZ_JACOBI) {
-      const T pz = DINV[l] * R[l];
-      P[l] = pz;
-      if (!OWN || OWN[l]) acc0 += (double)R[l] * (double)pz;
+      const T pz = dinvv[q] * rv[q];
+      vst(P, l, pz);
+      if (own[q]) acc0 += (double)rv[q] * (double)pz;
     } else if constexpr (OP == V_CHEB_INIT0) {
-      const T d = c0 * DINV[l] * R[l];
-      Dd[l] = d;
-      X[l] = d;
+      const T d = c0 * dinvv[q] * rv[q];
+      vst(Dd, l, d);
+      vst(X, l, d);
     } else if constexpr (OP == V_CHEB_INITX) {
-      const T res = R[l] - Tt[l];
-      RES[l] = res;
-      const T d = c0 * DINV[l] * res;
-      Dd[l] = d;
-      X[l] += d;
+      const T res = rv[q] - tv[q];
+      vst(RES, l, res);
+      const T d = c0 * dinvv[q] * res;
+      vst(Dd, l, d);
+      vst(X, l, xv[q] + d);
     } else if constexpr (OP == V_CHEB_STEP0) {
-      const T res = R[l] - Tt[l];
-      RES[l] = res;
-      const T d = c1 * Dd[l] + c2 * DINV[l] * res;
-      Dd[l] = d;
-      X[l] += d;
+      const T res = rv[q] - tv[q];
+      vst(RES, l, res);
+      const T d = c1 * dv[q] + c2 * dinvv[q] * res;
+      vst(Dd, l, d);
+      vst(X, l, xv[q] + d);
     } else if constexpr (OP == V_CHEB_STEP) {
-      const T res = RES[l] - Tt[l];
-      RES[l] = res;
-      const T d = c1 * Dd[l] + c2 * DINV[l] * res;
-      Dd[l] = d;
-      X[l] += d;
+      const T res = resv[q] - tv[q];
+      vst(RES, l, res);
+      const T d = c1 * dv[q] + c2 * dinvv[q] * res;
+      vst(Dd, l, d);
+      vst(X, l, xv[q] + d);
     } else if constexpr (OP == V_CHEB_INIT0D) {
-      Dd[l] = c0 * DINV[l] * R[l];
+      vst(Dd, l, c0 * dinvv[q] * rv[q]);
     } else if constexpr (OP == V_CHEB_INIT0D_IN64) {
-      const T rv = (T)gl(a.in64)[l];
-      R[l] = rv;
-      Dd[l] = c0 * DINV[l] * rv;
+      const T r = (T)in64v[q];
+      vst(R, l, r);
+      vst(Dd, l, c0 * dinvv[q] * r);
     } else if constexpr (OP == V_CHEB_STEP0X) {
-      const T res = R[l] - Tt[l];
-      RES[l] = res;
-      const T dold = Dd[l];
-      const T d = c1 * dold + c2 * DINV[l] * res;
-      Dd[l] = d;
-      X[l] = dold + d;
+      const T res = rv[q] - tv[q];
+      vst(RES, l, res);
+      const T dold = dv[q];
+      const T d = c1 * dold + c2 * dinvv[q] * res;
+      vst(Dd, l, d);
+      vst(X, l, dold + d);
     } else if constexpr (OP == V_CHEB_LAST0X) {
-      const T dold = Dd[l];
-      X[l] = dold + (c1 * dold + c2 * DINV[l] * (R[l] - Tt[l]));
+      const T dold = dv[q];
+      vst(X, l, dold + (c1 * dold + c2 * dinvv[q] * (rv[q] - tv[q])));
     } else if constexpr (OP == V_CHEB_LAST) {
-      X[l] += c1 * Dd[l] + c2 * DINV[l] * (RES[l] - Tt[l]);
+      vst(X, l, xv[q] + (c1 * dv[q] + c2 * dinvv[q] * (resv[q] - tv[q])));
     } else if constexpr (OP == V_CHEB_LAST_OUT64) {
-      const double zv = (double)(X[l] + (c1 * Dd[l] + c2 * DINV[l] * (RES[l] - Tt[l])));
-      gl(a.out64)[l] = zv;
-      if (!OWN || OWN[l]) {
-        acc0 += zv * gl(a.w64)[l];
-        acc1 += zv * gl(a.in64)[l];
+      const double z = (double)(xv[q] + (c1 * dv[q] + c2 * dinvv[q] * (resv[q] - tv[q])));
+      vst(gl(a.out64), l, z);
+      if (own[q]) {
+        acc0 += z * w64v[q];
+        acc1 += z * in64v[q];
       }
     } else if constexpr (OP == V_CHEB_INITX_LAST) {
-      X[l] += c0 * DINV[l] * (R[l] - Tt[l]);
+      vst(X, l, xv[q] + c0 * dinvv[q] * (rv[q] - tv[q]));
     } else if constexpr (OP == V_CHEB_INITX_OUT64) {
-      const double zv = (double)(X[l] + c0 * DINV[l] * (R[l] - Tt[l]));
-      gl(a.out64)[l] = zv;
-      if (!OWN || OWN[l]) {
-        acc0 += zv * gl(a.w64)[l];
-        acc1 += zv * gl(a.in64)[l];
+      const double z = (double)(xv[q] + c0 * dinvv[q] * (rv[q] - tv[q]));
+      vst(gl(a.out64), l, z);
+      if (own[q]) {
+        acc0 += z * w64v[q];
+        acc1 += z * in64v[q];
       }
     } else if constexpr (OP == V_RES0) {
-      RES[l] = R[l] - Tt[l];
+      vst(RES, l, rv[q] - tv[q]);
     } else if constexpr (OP == V_RES) {
-      RES[l] = RES[l] - Tt[l];
+      vst(RES, l, resv[q] - tv[q]);
     } else if constexpr (OP == V_CHEB_UPD) {
-      const T d = c1 * Dd[l] + c2 * DINV[l] * R[l];
-      Dd[l] = d;
-      X[l] += d;
+      const T d = c1 * dv[q] + c2 * dinvv[q] * rv[q];
+      vst(Dd, l, d);
+      vst(X, l, xv[q] + d);
     } else if constexpr (OP == V_CHEB_UPD0) {
-      const T d = c2 * DINV[l] * R[l];
-      Dd[l] = d;
-      X[l] += d;
+      const T d = c2 * dinvv[q] * rv[q];
+      vst(Dd, l, d);
+      vst(X, l, xv[q] + d);
     } else if constexpr (OP == V_CHEB_UPD_OUT64 || OP == V_CHEB_UPD0_OUT64) {
       T d;
-      if constexpr (OP == V_CHEB_UPD_OUT64) d = c1 * Dd[l] + c2 * DINV[l] * R[l];  // as V_CHEB_UPD
-      else d = c2 * DINV[l] * R[l];
-      const double zv = (double)(X[l] + d);
-      gl(a.out64)[l] = zv;
-      if (!OWN || OWN[l]) {
-        acc0 += zv * gl(a.w64)[l];
-        acc1 += zv * gl(a.in64)[l];
+      if constexpr (OP == V_CHEB_UPD_OUT64) d = c1 * dv[q] + c2 * dinvv[q] * rv[q];  // as V_CHEB_UPD
+      else d = c2 * dinvv[q] * rv[q];
+      const double z = (double)(xv[q] + d);
+      vst(gl(a.out64), l, z);
+      if (own[q]) {
+        acc0 += z * w64v[q];
+        acc1 += z * in64v[q];
       }
     } else if constexpr (OP == V_ZERO) {
-      X[l] = T(0);
+      vst(X, l, T(0));
     } else if constexpr (OP == V_FILL) {
-      X[l] = c0;
+      vst(X, l, c0);
     } else if constexpr (OP == V_COPY) {
-      X[l] = R[l];
+      vst(X, l, rv[q]);
     } else if constexpr (OP == V_SCALE_DINV) {
-      X[l] = DINV[l] * R[l];
+      vst(X, l, dinvv[q] * rv[q]);
     } else if constexpr (OP == V_NORMALIZE) {
-      X[l] = R[l] * scale;
+      vst(X, l, rv[q] * scale);
     } else if constexpr (OP == V_TRUE_RES) {
-      if (!OWN || OWN[l]) {
-        const double e = (double)R[l] - (double)Tt[l];
+      if (own[q]) {
+        const double e = (double)rv[q] - (double)tv[q];
         acc0 += e * e;
       }
     } else if constexpr (OP == V_DIV_DINV) {
-      X[l] = DINV[l] != T(0) ? R[l] / DINV[l] : T(0);
+      vst(X, l, dinvv[q] != T(0) ? rv[q] / dinvv[q] : T(0));
     } else if constexpr (OP == V_SCALE) {
-      X[l] = c0 * R[l];
+      vst(X, l, c0 * rv[q]);
     } else if constexpr (OP == V_AXPY) {
-      X[l] += c0 * R[l];
+      vst(X, l, xv[q] + c0 * rv[q]);
     }
   }
   constexpr bool RED = (OP == V_PCG_UPDATE || OP == V_DOT2 || OP == V_DOT1 || OP == V_RZ_JACOBI ||
