@@ -840,32 +840,62 @@ __global__ __launch_bounds__(kXferThreads) void k_xfer(Table<XferArgs<Tf, Tc>> t
   if (skipped(a.skip)) return;
   const int64_t e_first = (int64_t)lb * C::EPB;
   for (int t = threadIdx.x; t < NO * NI; t += kXferThreads) sM[t] = (Tf)Mg[t];
+  // prolongation: the fine values that receive the correction are loaded up
+  // front, so their latency overlaps the staging and the contraction
+  constexpr int KO = (C::EPB * C::S3 + kXferThreads - 1) / kXferThreads;
+  Tf xpre[KO];
+  if constexpr (DIR == 0) {
 #pragma unroll
-  for (int t = threadIdx.x; t < C::EPB * C::S0; t += kXferThreads) {
+    for (int k = 0; k < KO; ++k) {
+      const int t = threadIdx.x + k * kXferThreads;
+      const int el = t / C::S3, r = t - el * C::S3;
+      const int64_t e = e_first + el;
+      xpre[k] = (t < C::EPB * C::S3 && e < a.E) ? __builtin_nontemporal_load(gl(a.xf) + e * C::S3 + r) : Tf(0);
+    }
+  }
+  // staging: every input of the thread's points loaded before any LDS store
+  constexpr int KI = (C::EPB * C::S0 + kXferThreads - 1) / kXferThreads;
+  Tf vin[KI], tin[KI];
+  uint8_t oin[KI];
+#pragma unroll
+  for (int k = 0; k < KI; ++k) {
+    const int t = threadIdx.x + k * kXferThreads;
     const int el = t / C::S0, r = t - el * C::S0;
     const int64_t e = e_first + el;
-    Tf v = 0;
-    if (e < a.E) {
+    vin[k] = Tf(0);
+    tin[k] = Tf(0);
+    oin[k] = 0;
+    if (t < C::EPB * C::S0 && e < a.E) {
       const int64_t g = e * C::S0 + r;
       if constexpr (DIR == 0) {
-        v = (Tf)gl(a.zc)[a.umap_c ? (int64_t)gl(a.umap_c)[g] : g];
+        vin[k] = (Tf)gl(a.zc)[a.umap_c ? (int64_t)gl(a.umap_c)[g] : g];
       } else {
-        v = gl(a.rf)[g];
-        if (a.tf) v -= gl(a.tf)[g];
-        if (!gl(a.owner_f)[g]) v = 0;
+        vin[k] = __builtin_nontemporal_load(gl(a.rf) + g);
+        if (a.tf) tin[k] = __builtin_nontemporal_load(gl(a.tf) + g);
+        oin[k] = __builtin_nontemporal_load(gl(a.owner_f) + g);
       }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < KI; ++k) {
+    const int t = threadIdx.x + k * kXferThreads;
+    if (t >= C::EPB * C::S0) break;
+    const int el = t / C::S0, r = t - el * C::S0;
+    Tf v = vin[k];
+    if constexpr (DIR == 1) v = oin[k] ? v - tin[k] : Tf(0);
     s0[el][r] = v;
   }
   __syncthreads();
   tensor3<NI, NO, Tf>(sM, s0, s1, s2, s3);
 #pragma unroll
-  for (int t = threadIdx.x; t < C::EPB * C::S3; t += kXferThreads) {
+  for (int k = 0; k < KO; ++k) {
+    const int t = threadIdx.x + k * kXferThreads;
+    if (t >= C::EPB * C::S3) break;
     const int el = t / C::S3, r = t - el * C::S3;
     const int64_t e = e_first + el;
     if (e >= a.E) continue;
     const int64_t g = e * C::S3 + r;
-    if constexpr (DIR == 0) gl(a.xf)[g] += s3[el][r];
+    if constexpr (DIR == 0) __builtin_nontemporal_store(xpre[k] + s3[el][r], gl(a.xf) + g);
     else gl(a.out_c)[g] = (Tc)s3[el][r];
   }
 }
