@@ -918,6 +918,16 @@ static std::unique_ptr<Plan> make_plan(const std::vector<Slot*>& slots, bool ini
 // ---------------------------------------------------------------------------
 }  // namespace sem
 
+// An asynchronous look at the slots' flags: a copy of the flag block into
+// pinned memory queued behind the work so far, and an event after it. The
+// host queues more work before waiting on the event, so the device never
+// drains while the host reads convergence flags.
+struct sem_probe {
+  void* host = nullptr;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+
 struct sem_batch_s {
   hipStream_t stream = nullptr;
   int max_slots = 0;
@@ -927,12 +937,18 @@ struct sem_batch_s {
   size_t ctrl_bytes = 0;
   std::unique_ptr<sem::Plan> plan;
   bool dirty = true;
+  sem_probe probe_outer, probe_coarse;  // separate channels: a coarse loop runs while an outer probe is pending
 
   size_t scal_bytes() const { return sizeof(double) * 2 * sem::S_COUNT * max_slots; }
+  size_t flag_bytes() const { return sizeof(int) * 2 * sem::F_COUNT * max_slots; }
   ~sem_batch_s() {
     if (stream) (void)hipStreamSynchronize(stream);
     for (auto& s : slots) sem::pool_put(s.ws, s.ws_bytes);
     if (host_ctrl) (void)hipHostFree(host_ctrl);
+    for (sem_probe* p : {&probe_outer, &probe_coarse}) {
+      if (p->host) (void)hipHostFree(p->host);
+      if (p->ev) (void)hipEventDestroy(p->ev);
+    }
   }
 };
 
@@ -946,6 +962,10 @@ static void batch_init(sem_batch_s* B, int max_slots, hipStream_t s) {
   B->ctrl.alloc(B->ctrl_bytes);
   SEM_HIP(hipMemsetAsync(B->ctrl.p, 0, B->ctrl_bytes, s));
   SEM_HIP(hipHostMalloc(&B->host_ctrl, B->ctrl_bytes, hipHostMallocDefault));
+  for (sem_probe* p : {&B->probe_outer, &B->probe_coarse}) {
+    SEM_HIP(hipHostMalloc(&p->host, B->flag_bytes(), hipHostMallocDefault));
+    SEM_HIP(hipEventCreateWithFlags(&p->ev, hipEventDisableTiming));
+  }
   for (int k = 0; k < max_slots; ++k) {
     Slot& sl = B->slots[k];
     sl.idx = k;
@@ -970,28 +990,53 @@ static const int* host_flags(sem_batch_s* B, int k, int stage) {
          (size_t)2 * F_COUNT * k + (size_t)stage * F_COUNT;
 }
 
+static void probe_post(sem_batch_s* B, sem_probe& p) {
+  if (p.pending) fail(SEM_EHIP, "internal: a probe is already pending");
+  SEM_HIP(hipMemcpyAsync(p.host, B->ctrl.as<uint8_t>() + B->scal_bytes(), B->flag_bytes(), hipMemcpyDeviceToHost,
+                         B->stream));
+  SEM_HIP(hipEventRecord(p.ev, B->stream));
+  p.pending = true;
+}
+// waits for the pending probe; returns its flag block
+static const int* probe_wait(sem_probe& p) {
+  SEM_HIP(hipEventSynchronize(p.ev));
+  p.pending = false;
+  return static_cast<const int*>(p.host);
+}
+static const int* probe_flags(const int* block, int k, int stage) {
+  return block + (size_t)2 * F_COUNT * k + (size_t)stage * F_COUNT;
+}
+
 static void run(const std::vector<Fn>& seq, hipStream_t s) {
   for (const Fn& f : seq) f(s);
 }
 
-// one pass of every group's body; the coarse loop polls its done flags
+// one pass of every group's body. The coarse loop is queued in chunks; after
+// queuing chunk k+1 the host reads the flags probed after chunk k, so it is
+// always one chunk ahead of the device (a chunk queued after the last problem
+// finished runs as no-ops: its launches skip finished problems).
 static void run_body(sem_batch_s* B, Plan& P) {
   for (Group& g : P.groups) {
     run(g.head, B->stream);
     if (!g.cinit.empty()) {
       run(g.cinit, B->stream);
+      sem_probe& pr = B->probe_coarse;
       int ran = 0;
       while (ran < g.coarse_limit) {
         const int chunk = g.coarse_fixed > 0 ? g.coarse_limit : std::min(g.coarse_check, g.coarse_limit - ran);
         for (int k = 0; k < chunk; ++k) run(g.citer, B->stream);
         ran += chunk;
+        if (pr.pending) {
+          const int* fl = probe_wait(pr);
+          bool all = true;
+          for (Slot* s : g.S)
+            if (!probe_flags(fl, s->idx, 0)[F_DONE] && !probe_flags(fl, s->idx, 1)[F_DONE]) all = false;
+          if (all) break;
+        }
         if (ran >= g.coarse_limit) break;
-        fetch_ctrl(B);
-        bool all = true;
-        for (Slot* s : g.S)
-          if (!host_flags(B, s->idx, 0)[F_DONE] && !host_flags(B, s->idx, 1)[F_DONE]) all = false;
-        if (all) break;
+        probe_post(B, pr);
       }
+      if (pr.pending) (void)probe_wait(pr);
     }
     run(g.tail, B->stream);
   }
@@ -1215,10 +1260,30 @@ static int solve_many(int n, const sem_mesh* m, const sem_pmg* p, const double* 
   int64_t cap = 0;
   for (int k = 0; k < n; ++k) cap = std::max<int64_t>(cap, std::max(B.slots[k].o.maxit, B.slots[k].o.fixed_iters));
   int64_t ran = 0;
-  // the device marks every problem done by maxit; the host bound is a backstop
-  while (batch_step(&B, every) > 0) {
-    ran += every;
-    if (ran > cap + 2 * every + 8) fail(SEM_EHIP, "solve: device convergence flags did not settle");
+  // the first step initialises every problem (and retires those done at once);
+  // after it the host stays one step ahead: it queues step k+1 before reading
+  // the flags probed after step k, and a step queued after the last problem
+  // finished runs as no-ops. The device marks every problem done by maxit;
+  // the host bound is a backstop.
+  if (batch_step(&B, every) > 0) {
+    sem_probe& pr = B.probe_outer;
+    while (true) {
+      for (int it = 0; it < every; ++it) run_body(&B, *B.plan);
+      ran += every;
+      if (pr.pending) {
+        const int* fl = probe_wait(pr);
+        bool all = true;
+        for (const Slot& s : B.slots)
+          if (s.state == 2 && !probe_flags(fl, s.idx, 0)[F_DONE]) all = false;
+        if (all) break;
+      }
+      if (ran > cap + 2 * every + 8) fail(SEM_EHIP, "solve: device convergence flags did not settle");
+      probe_post(&B, pr);
+    }
+    if (pr.pending) (void)probe_wait(pr);
+    fetch_ctrl(&B);
+    for (Slot& s : B.slots)
+      if (s.state == 2) finish_slot(&B, s);
   }
   int worst = SEM_OK;
   const double secs = std::chrono::duration<double>(Clock::now() - t0).count();
