@@ -94,6 +94,7 @@ struct Slot {
        *lt[kMaxLevels] = {};
   void *ls[kMaxLevels] = {}, *lovl[kMaxLevels] = {};  // Schwarz smoother: output and face overlaps
   double *cr = nullptr, *cx = nullptr, *cp = nullptr, *cw = nullptr;
+  double* cz = nullptr;   // D^-1 r of the assembled coarse CG
   double* clocal = nullptr;  // restriction output on coarse element storage (assembled coarse level)
   double* dinv_h = nullptr;  // Jacobi-PCG: inverse diagonal of A + lambda B (Helmholtz solves)
   double* partial = nullptr;
@@ -155,6 +156,7 @@ size_t layout(Slot& s, uint8_t* base) {
     s.cp = (double*)take(8 * nc);
     s.cw = (double*)take(8 * nc);
     if (c.assembled) {
+      s.cz = (double*)take(8 * nc);
       s.clocal = (double*)take(8 * c.nloc);
       stride = std::max<int64_t>(stride, std::max<int64_t>(spmv_blocks(nc), vec_blocks(nc)));
     } else {
@@ -321,30 +323,6 @@ class Plan {
     add(seq, args, starts, [op, total](const Table<VecArgs<T>>& t, hipStream_t st) { launch_vec<T>(op, t, total, st); });
   }
 
-  // y = A x on the unique DOFs of assembled level l (optionally the partials of x . y)
-  template <typename FX, typename FY>
-  void spmv(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, FX x_of, FY y_of, bool with_partial,
-            int skip_mode, int region = 0) {
-    std::vector<SpmvArgs> args;
-    std::vector<int> starts{0};
-    for (Slot* s : S) {
-      const MeshData& m = s->level(l);
-      SpmvArgs a;
-      a.n = m.n_unique;
-      a.W = m.ell_w;
-      a.col = m.ell_col.as<int>();
-      a.val = m.ell_val.as<double>();
-      a.x = x_of(*s);
-      a.y = y_of(*s);
-      a.partial = with_partial ? s->partial + region * s->stride : nullptr;
-      a.skip = skip(*s, skip_mode);
-      args.push_back(a);
-      starts.push_back(starts.back() + (int)spmv_blocks(a.n));
-    }
-    const int64_t total = starts.back();
-    add(seq, args, starts, [total](const Table<SpmvArgs>& t, hipStream_t st) { launch_spmv(t, total, st); });
-  }
-
   // out (unique DOFs) = masked sum of the element-storage copies in `in`
   template <typename FI, typename FO>
   void usum(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, FI in_of, FO out_of, int skip_mode) {
@@ -491,7 +469,8 @@ class Plan {
     gs<T>(seq, S, l, out_of, skip_mode);
   }
 
-  // one coarse CG iteration on unique DOFs of level l (parity par): p update, SpMV, x/r update
+  // one coarse CG iteration on unique DOFs of level l (parity par): p update fused
+  // with the SpMV, then the x/r update
   void cg_iteration(std::vector<Fn>& seq, const std::vector<Slot*>& S, int l, int par, const sem_pmg_opts& o) {
     std::vector<CgArgs> args;
     std::vector<int> st_up{0};
@@ -506,8 +485,8 @@ class Plan {
       a.x = s->cx;
       a.r = s->cr;
       a.w = s->cw;
-      a.p_old = s->cp;
-      a.p_new = s->cp;
+      a.p = s->cp;
+      a.z = s->cz;
       a.partial = s->partial;
       a.stride = s->stride;
       a.nblk_upd = cg_update_blocks(a.n);
@@ -524,8 +503,7 @@ class Plan {
       st_up.push_back(st_up.back() + (int)a.nblk_upd);
     }
     const int64_t tup = st_up.back();
-    add(seq, args, st_up, [tup](const Table<CgArgs>& t, hipStream_t st) { launch_cg_pupdate(t, tup, st); });
-    spmv(seq, S, l, [](Slot& s) { return (const double*)s.cp; }, [](Slot& s) { return s.cw; }, true, 2, 2);
+    add(seq, args, st_up, [tup](const Table<CgArgs>& t, hipStream_t st) { launch_cg_pspmv(t, tup, st); });
     add(seq, args, st_up, [tup](const Table<CgArgs>& t, hipStream_t st) { launch_cg_update(t, tup, st); });
   }
 
@@ -738,9 +716,9 @@ void Plan::build_vcycle(Group& g) {
     vec<double>(g.cinit, S, c, V_ZERO, [](Slot& s, VecArgs<double>& a) { a.x = s.cx; }, SK, U);
     vec<double>(g.cinit, S, c, V_DOT1, [](Slot& s, VecArgs<double>& a) { a.r = s.cr; }, SK, U);
     fin(g.cinit, S, FIN_INIT, 1, nvec, SK);
-    vec<double>(g.cinit, S, c, V_RZ_JACOBI, [cdinv](Slot& s, VecArgs<double>& a) {
+    vec<double>(g.cinit, S, c, V_RZ_JACOBI, [cdinv, U](Slot& s, VecArgs<double>& a) {
       a.r = s.cr;
-      a.p = s.cp;
+      a.p = U ? s.cz : s.cp;  // assembled: z = D^-1 r, which the first SpMV gathers
       a.dinv = cdinv(s);
     }, SK, U);
     fin(g.cinit, S, FIN_RZ, 1, nvec, SK);

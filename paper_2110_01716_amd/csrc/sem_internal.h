@@ -283,18 +283,6 @@ struct XferArgs {
   Skip skip;
 };
 
-// y = A x on unique DOFs (ELL), partial per block: sum x . y
-struct SpmvArgs {
-  int64_t n = 0;
-  int W = 0;
-  const int* col = nullptr;
-  const double* val = nullptr;
-  const double* x = nullptr;
-  double* y = nullptr;
-  double* partial = nullptr;
-  Skip skip;
-};
-
 // out[r] = 0 on Dirichlet DOFs, else sum of the local copies of DOF r (Q^T)
 struct UsumArgs {
   int64_t n = 0;
@@ -348,15 +336,15 @@ struct SchwarzInfoArgs {
   double* lengths = nullptr;
 };
 
-// Coarse-grid Jacobi-PCG on the unique DOFs of an assembled level with no
-// finalize launches (parity `par` alternates the ring slots of rz and of the
-// iteration counter, so no launch overwrites a value its own blocks read):
-//  k_cg_pupdate: every block reduces the previous update's partials (r.r,
-//                r.D^-1 r) in a fixed order, tests convergence, forms beta,
-//                then p = D^-1 r + beta p
-//  k_spmv:       w = A p, partial p . w
-//  k_cg_update:  every block reduces the p . w partials, alpha = rz / pw;
-//                x += alpha p, r -= alpha w, partials r.r and r.D^-1 r
+// Coarse-grid Jacobi-PCG on the unique DOFs of an assembled level in two
+// launches per iteration and no finalize launch (parity `par` alternates the
+// ring slots of rz and of the iteration counter, so no launch overwrites a
+// value its own blocks read):
+//  k_cg_pspmv:  every block reduces the previous update's partials (r.r,
+//               r.z) in a fixed order, tests convergence, forms beta; then
+//               q = A z, p = z + beta p, w = q + beta w row by row, partial p . w
+//  k_cg_update: every block reduces the p . w partials, alpha = rz / pw;
+//               x += alpha p, r -= alpha w, z = D^-1 r, partials r.r and r.z
 struct CgArgs {
   int64_t n = 0;
   int W = 0;
@@ -366,12 +354,12 @@ struct CgArgs {
   double* x = nullptr;
   double* r = nullptr;
   double* w = nullptr;
-  const double* p_old = nullptr;  // p before and after k_cg_pupdate (may alias)
-  double* p_new = nullptr;
+  double* p = nullptr;
+  double* z = nullptr;        // D^-1 r (written by the update, gathered by the SpMV)
   double* partial = nullptr;  // regions 0: r.r, 1: r.D^-1 r (update), 2: p.w (spmv)
   int64_t stride = 0;
   int64_t nblk_upd = 0;       // blocks of k_cg_update (partials in regions 0, 1)
-  int64_t nblk_sp = 0;        // blocks of k_spmv (partials in region 2)
+  int64_t nblk_sp = 0;        // blocks of k_cg_pspmv (partials in region 2)
   double* scal = nullptr;     // coarse stage scalars (S_BB, ring S_RZ / S_RZ_NEW, ...)
   int* flags = nullptr;       // coarse stage flags (ring F_ITERS / F_ITERS2, ...)
   int* total = nullptr;       // outer stage F_TOTAL (coarse iterations of the solve)
@@ -433,10 +421,10 @@ void launch_schwarz(int N, int mode, const Table<SchwarzArgs<T>>& t, int64_t tot
 template <typename T>
 void launch_schwarz_pull(int N, const Table<SchwarzPullArgs<T>>& t, int64_t total_blocks, hipStream_t s);
 void launch_schwarz_info(const SchwarzInfoArgs& a, hipStream_t s);
-void launch_spmv(const Table<SpmvArgs>& t, int64_t total_blocks, hipStream_t s);
 int64_t cg_update_blocks(int64_t n);
-void launch_cg_pupdate(const Table<CgArgs>& t, int64_t total_blocks, hipStream_t s); // blocks: cg_update_blocks(n)
 void launch_cg_update(const Table<CgArgs>& t, int64_t total_blocks, hipStream_t s); // blocks: cg_update_blocks(n)
+// p update and w = A p in one launch (p_old != p_new); blocks: cg_update_blocks(n)
+void launch_cg_pspmv(const Table<CgArgs>& t, int64_t total_blocks, hipStream_t s);
 void launch_usum(const Table<UsumArgs>& t, int64_t total_blocks, hipStream_t s);
 template <typename Tf, typename Tc>
 void launch_xfer(int dir, int Nf, int Nc, const Table<XferArgs<Tf, Tc>>& t, int64_t total_blocks,

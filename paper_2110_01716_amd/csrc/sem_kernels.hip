@@ -16,7 +16,7 @@
 //              scalar recurrences (alpha, beta, convergence tests).
 //  * k_xfer    pMG prolongation (J x J x J) and restriction (transpose), sum
 //              factorised in LDS (Implementation, pMG paragraph).
-//  * k_spmv, k_cg_pupdate, k_cg_update
+//  * k_cg_pspmv, k_cg_update
 //              coarse-level Jacobi-PCG on the assembled N=1 operator.
 //  * k_schwarz_mfma, k_schwarz, k_schwarz_pull
 //              overlapping Schwarz smoother: fast-diagonalization solve on
@@ -949,49 +949,6 @@ constexpr int kSpThreads = 256;
 
 int64_t spmv_blocks(int64_t n) { return (n + kSpThreads - 1) / kSpThreads; }
 
-__global__ __launch_bounds__(kSpThreads) void k_spmv(Table<SpmvArgs> tab) {
-  int lb;
-  const SpmvArgs a = fetch_args(tab, blockIdx.x, lb);
-  if (skipped(a.skip)) return;
-  const int64_t r = (int64_t)lb * kSpThreads + threadIdx.x;
-  double d = 0.0;
-  if (r < a.n) {
-    const SEM_GLOBAL int* col = gl(a.col) + r;
-    const SEM_GLOBAL double* val = gl(a.val) + r;
-    const SEM_GLOBAL double* x = gl(a.x);
-    // issue the row's (value, column) loads in groups of 9, then the gathers
-    double y = 0.0;
-    int k = 0;
-    for (; k + 9 <= a.W; k += 9) {
-      double v[9];
-      int c[9];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {  // the matrix is re-read every coarse iteration: keep it cached
-        v[q] = val[(int64_t)(k + q) * a.n];
-        c[q] = col[(int64_t)(k + q) * a.n];
-      }
-      double xv[9];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) xv[q] = x[c[q]];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) y += v[q] * xv[q];
-    }
-    for (; k < a.W; ++k) y += val[(int64_t)k * a.n] * x[col[(int64_t)k * a.n]];
-    gl(a.y)[r] = y;
-    d = x[r] * y;
-  }
-  if (a.partial) {
-    __shared__ double s_red[kSpThreads / 64];
-    const double s = block_sum<kSpThreads>(d, s_red);
-    if (threadIdx.x == 0) gl(a.partial)[lb] = s;
-  }
-}
-
-void launch_spmv(const Table<SpmvArgs>& t, int64_t total_blocks, hipStream_t s) {
-  if (total_blocks <= 0) return;
-  hipLaunchKernelGGL(k_spmv, dim3((unsigned)total_blocks), dim3(kSpThreads), 0, s, t);
-  SEM_HIP(hipGetLastError());
-}
 
 // ---------------------------------------------------------------------------
 // coarse-grid Jacobi-PCG, two launches per iteration (see CgArgs)
@@ -1024,7 +981,15 @@ __device__ __forceinline__ void block_sums2(const SEM_GLOBAL double* part, int64
   }
 }
 
-__global__ __launch_bounds__(kCgThreads) void k_cg_pupdate(Table<CgArgs> tab) {
+// The p update fused into the SpMV. Every block decides convergence and beta
+// (redundantly, from the same partials in the same order); then, with
+// z = D^-1 r stored by the previous update, each row forms q_r = sum_k A_rk z_k
+// and the new direction and its image row by row:
+//   p_r = z_r + beta p_r,   w_r = q_r + beta w_r   (= (A p)_r),
+// the block's partial of p . w included. Only z is gathered, and p and w are
+// updated in place, so no block reads a value another block of the launch
+// writes.
+__global__ __launch_bounds__(kCgThreads) void k_cg_pspmv(Table<CgArgs> tab) {
   __shared__ double red[2][kCgThreads / 64];
   __shared__ int s_go;
   __shared__ double s_beta;
@@ -1068,11 +1033,39 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_pupdate(Table<CgArgs> tab) {
     fl[a.par ? F_ITERS : F_ITERS2] = it + 1;
     if (a.total) ++(*gl(a.total));
   }
+  const SEM_GLOBAL double* zv = gl(a.z);
   const int64_t i = (int64_t)lb * kCgThreads + threadIdx.x;
+  double d = 0.0;
   if (i < a.n) {
-    const double z = gl(a.dinv)[i] * gl(a.r)[i];
-    gl(a.p_new)[i] = first ? z : z + beta * gl(a.p_old)[i];
+    const SEM_GLOBAL int* col = gl(a.col) + i;
+    const SEM_GLOBAL double* val = gl(a.val) + i;
+    double q = 0.0;
+    int k = 0;
+    for (; k + 9 <= a.W; k += 9) {
+      double v[9];
+      int c[9];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {  // the matrix is re-read every coarse iteration: keep it cached
+        v[j] = val[(int64_t)(k + j) * a.n];
+        c[j] = col[(int64_t)(k + j) * a.n];
+      }
+      double zc[9];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) zc[j] = zv[c[j]];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) q += v[j] * zc[j];
+    }
+    for (; k < a.W; ++k) q += val[(int64_t)k * a.n] * zv[col[(int64_t)k * a.n]];
+    SEM_GLOBAL double* P = gl(a.p);
+    SEM_GLOBAL double* Wv = gl(a.w);
+    const double pi = first ? zv[i] : zv[i] + beta * P[i];
+    const double wi = first ? q : q + beta * Wv[i];
+    P[i] = pi;
+    Wv[i] = wi;
+    d = pi * wi;
   }
+  const double sblk = block_sum<kCgThreads>(d, red[0]);
+  if (threadIdx.x == 0) gl(a.partial)[2 * a.stride + lb] = sblk;
 }
 
 __global__ __launch_bounds__(kCgThreads) void k_cg_update(Table<CgArgs> tab) {
@@ -1093,12 +1086,14 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_update(Table<CgArgs> tab) {
   const int64_t i = (int64_t)lb * kCgThreads + threadIdx.x;
   double rr = 0.0, rz = 0.0;
   if (i < a.n) {
-    const double pi = gl(a.p_new)[i];
+    const double pi = gl(a.p)[i];
     gl(a.x)[i] += alpha * pi;
     const double rn = gl(a.r)[i] - alpha * gl(a.w)[i];
     gl(a.r)[i] = rn;
+    const double zn = gl(a.dinv)[i] * rn;
+    gl(a.z)[i] = zn;  // the next iteration's SpMV gathers z
     rr = rn * rn;
-    rz = rn * gl(a.dinv)[i] * rn;
+    rz = zn * rn;
   }
   __syncthreads();  // red is reused
   double s0 = wave_sum(rr), s1 = wave_sum(rz);
@@ -1118,9 +1113,9 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_update(Table<CgArgs> tab) {
   }
 }
 
-void launch_cg_pupdate(const Table<CgArgs>& t, int64_t total_blocks, hipStream_t s) {
+void launch_cg_pspmv(const Table<CgArgs>& t, int64_t total_blocks, hipStream_t s) {
   if (total_blocks <= 0) return;
-  hipLaunchKernelGGL(k_cg_pupdate, dim3((unsigned)total_blocks), dim3(kCgThreads), 0, s, t);
+  hipLaunchKernelGGL(k_cg_pspmv, dim3((unsigned)total_blocks), dim3(kCgThreads), 0, s, t);
   SEM_HIP(hipGetLastError());
 }
 
