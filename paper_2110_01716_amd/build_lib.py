@@ -1,10 +1,16 @@
 """Build libsem.so (HIP for gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2110_01716_amd.build_lib [--jobs N] [--debug]
+Usage: python -m paper_2110_01716_amd.build_lib [--jobs N] [--debug] [--sanitize]
 
 Every source under csrc/ is compiled with hipcc --offload-arch=gfx950 and
 linked into paper_2110_01716_amd/libsem.so. Always rebuilds (the build check
 must compile every time it is asked to).
+
+--sanitize builds a second copy of the library with its host code under
+AddressSanitizer and UndefinedBehaviorSanitizer (device code is not
+instrumented) into _build_san/libsem_san.so, and the driver
+tests/sanitize/sem_sanitize_driver.cpp linked against it into
+_build_san/sem_sanitize_driver (run it on a machine with the GPU).
 """
 from __future__ import annotations
 
@@ -22,6 +28,11 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsem.so")
+BUILD_SAN = os.path.join(PKG, "_build_san")
+DRIVER_SAN = os.path.join(ROOT, "tests", "sanitize", "sem_sanitize_driver.cpp")
+# host-only instrumentation: each sanitizer flag applies to the host pass alone
+SAN_FLAGS = ["-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
 
 ARCH = os.environ.get("SEM_OFFLOAD_ARCH", "gfx950")
 
@@ -49,8 +60,8 @@ def sources():
     return out
 
 
-def compile_one(src: str, extra: list[str]) -> tuple[str, float]:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def compile_one(src: str, extra: list[str], out_dir: str = BUILD) -> tuple[str, float]:
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
     cmd = [hipcc(), *COMMON, *extra, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
@@ -89,12 +100,46 @@ def build(jobs: int | None = None, debug: bool = False, verbose: bool = True) ->
     return LIB
 
 
+def build_sanitized(jobs: int | None = None, verbose: bool = True) -> str:
+    """Host-ASan/UBSan copy of the library plus the driver that exercises it."""
+    os.makedirs(BUILD_SAN, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
+    objs = []
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = {ex.submit(compile_one, s, SAN_FLAGS, BUILD_SAN): s for s in srcs}
+        for fu in cf.as_completed(futs):
+            obj, dt = fu.result()
+            objs.append(obj)
+            if verbose:
+                print(f"  compiled {os.path.basename(futs[fu])} (sanitized) in {dt:.1f}s", flush=True)
+    lib = os.path.join(BUILD_SAN, "libsem_san.so")
+    drv_obj = os.path.join(BUILD_SAN, "sem_sanitize_driver.o")
+    steps = [
+        [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *SAN_FLAGS, *sorted(objs), "-o", lib],
+        [hipcc(), *COMMON, *SAN_FLAGS, "-c", DRIVER_SAN, "-o", drv_obj],
+        [hipcc(), f"--offload-arch={ARCH}", *SAN_FLAGS, drv_obj, lib, f"-Wl,-rpath,{BUILD_SAN}",
+         "-o", os.path.join(BUILD_SAN, "sem_sanitize_driver")],
+    ]
+    for cmd in steps:
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"sanitized build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"  linked {lib} and {os.path.join(BUILD_SAN, 'sem_sanitize_driver')}", flush=True)
+    return lib
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--debug", action="store_true")
+    ap.add_argument("--sanitize", action="store_true", help="host-sanitized library and driver (_build_san/)")
     a = ap.parse_args()
-    build(a.jobs, a.debug)
+    if a.sanitize:
+        build_sanitized(a.jobs)
+    else:
+        build(a.jobs, a.debug)
 
 
 if __name__ == "__main__":
