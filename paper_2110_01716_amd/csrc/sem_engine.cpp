@@ -1020,26 +1020,6 @@ static void run_body(sem_batch_s* B, Plan& P) {
   }
 }
 
-static double true_relres(Slot& s, hipStream_t st) {
-  const MeshData& m = s.level(0);
-  apply_H(m, s.lam(), s.x, s.w, st);
-  Table<VecArgs<double>> t;
-  t.one.n = m.nloc;
-  t.one.r = const_cast<double*>(s.b);
-  t.one.t = s.w;
-  t.one.owner = m.owner.as<uint8_t>();
-  t.one.partial = s.partial;
-  t.one.stride = s.stride;
-  const int64_t nb = vec_blocks(m.nloc);
-  launch_vec<double>(V_TRUE_RES, t, nb, st);
-  std::vector<double> h(nb);
-  SEM_HIP(hipMemcpyAsync(h.data(), s.partial, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
-  SEM_HIP(hipStreamSynchronize(st));
-  double sum = 0.0;
-  for (double v : h) sum += v;
-  return sum;
-}
-
 static void batch_add(sem_batch_s* B, sem_mesh m, sem_pmg p, const double* b, double* x, const sem_solve_opts* oin,
                       int* slot_out) {
   if (!m || !b || !x) fail(SEM_EINVAL, "batch add: NULL argument");
@@ -1091,21 +1071,43 @@ static void batch_release(sem_batch_s* B, int k) {
   s.pmg = nullptr;
 }
 
-static void finish_slot(sem_batch_s* B, Slot& s) {
-  const double* sc = host_scal(B, s.idx, 0);
-  const int* fl = host_flags(B, s.idx, 0);
-  s.info.iters = fl[F_ITERS];
-  s.info.status = fl[F_STATUS];
-  s.info.relres = sc[S_RELRES];
-  s.info.coarse_iters = fl[F_TOTAL];
-  const double bb = sc[S_BB];
-  if (bb > 0 && std::isfinite(bb) && s.info.status != SEM_ENAN) {
-    s.info.relres_true = std::sqrt(true_relres(s, B->stream) / bb);
-  } else {
-    s.info.relres_true = (bb == 0) ? 0.0 : NAN;
+// Retire finished solves: their info from the fetched flags, and the true
+// residual ||b - H x|| of all of them in one pass (one launch per kernel over
+// every slot, one reduction per slot, one copy back) instead of one
+// synchronised pass per slot. The caller has fetched the control block.
+static void finish_slots(sem_batch_s* B, const std::vector<Slot*>& S) {
+  std::vector<Slot*> need;
+  for (Slot* s : S) {
+    const double* sc = host_scal(B, s->idx, 0);
+    const int* fl = host_flags(B, s->idx, 0);
+    s->info.iters = fl[F_ITERS];
+    s->info.status = fl[F_STATUS];
+    s->info.relres = sc[S_RELRES];
+    s->info.coarse_iters = fl[F_TOTAL];
+    const double bb = sc[S_BB];
+    if (bb > 0 && std::isfinite(bb) && s->info.status != SEM_ENAN) need.push_back(s);
+    else s->info.relres_true = (bb == 0) ? 0.0 : NAN;
   }
-  s.info.seconds = std::chrono::duration<double>(Clock::now() - s.t0).count();
-  s.state = 3;
+  if (!need.empty()) {
+    Plan P;
+    std::vector<Fn> seq;
+    P.apply_A<double>(seq, need, 0, [](Slot& s) { return (const double*)s.x; }, [](Slot& s) { return s.w; }, false, 0);
+    P.vec<double>(seq, need, 0, V_TRUE_RES, [](Slot& s, VecArgs<double>& a) {
+      a.r = const_cast<double*>(s.b);
+      a.t = s.w;
+    }, 0);
+    P.fin(seq, need, FIN_STORE, 0, [](Slot& s) { return vec_blocks(s.level(0).nloc); }, 0);
+    P.upload(B->stream);
+    run(seq, B->stream);
+    fetch_ctrl(B);  // also waits before P's tables are freed
+    for (Slot* s : need)
+      s->info.relres_true = std::sqrt(host_scal(B, s->idx, 0)[S_TMP] / host_scal(B, s->idx, 0)[S_BB]);
+  }
+  const auto now = Clock::now();
+  for (Slot* s : S) {
+    s->info.seconds = std::chrono::duration<double>(now - s->t0).count();
+    s->state = 3;
+  }
 }
 
 static int batch_step(sem_batch_s* B, int iters) {
@@ -1127,10 +1129,11 @@ static int batch_step(sem_batch_s* B, int iters) {
   // problems that are already done after init (zero or NaN rhs) retire now
   fetch_ctrl(B);
   {
-    std::vector<Slot*> still;
-    for (Slot* s : act) {
-      if (host_flags(B, s->idx, 0)[F_DONE]) { finish_slot(B, *s); B->dirty = true; }
-      else still.push_back(s);
+    std::vector<Slot*> still, done;
+    for (Slot* s : act) (host_flags(B, s->idx, 0)[F_DONE] ? done : still).push_back(s);
+    if (!done.empty()) {
+      finish_slots(B, done);
+      B->dirty = true;
     }
     act.swap(still);
   }
@@ -1142,16 +1145,14 @@ static int batch_step(sem_batch_s* B, int iters) {
   }
   for (int it = 0; it < iters; ++it) run_body(B, *B->plan);
   fetch_ctrl(B);
-  int n_active = 0;
-  for (Slot* s : act) {
-    if (host_flags(B, s->idx, 0)[F_DONE]) {
-      finish_slot(B, *s);
-      B->dirty = true;
-    } else {
-      ++n_active;
-    }
+  std::vector<Slot*> done;
+  for (Slot* s : act)
+    if (host_flags(B, s->idx, 0)[F_DONE]) done.push_back(s);
+  if (!done.empty()) {
+    finish_slots(B, done);
+    B->dirty = true;
   }
-  return n_active;
+  return (int)(act.size() - done.size());
 }
 
 }  // namespace sem
@@ -1260,8 +1261,10 @@ static int solve_many(int n, const sem_mesh* m, const sem_pmg* p, const double* 
     }
     if (pr.pending) (void)probe_wait(pr);
     fetch_ctrl(&B);
+    std::vector<Slot*> done;
     for (Slot& s : B.slots)
-      if (s.state == 2) finish_slot(&B, s);
+      if (s.state == 2) done.push_back(&s);
+    finish_slots(&B, done);
   }
   int worst = SEM_OK;
   const double secs = std::chrono::duration<double>(Clock::now() - t0).count();
