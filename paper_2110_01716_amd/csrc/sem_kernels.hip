@@ -140,7 +140,7 @@ template <int N>
 struct AxCfg {
   static constexpr int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
   static constexpr int EPB = N == 1 ? 64 : N == 2 ? 28 : N == 3 ? 16 : N == 4 ? 10 : N == 5 ? 7
-                           : N == 6 ? 5 : N == 7 ? 1 : N == 8 ? 3 : N == 9 ? 2 : N == 10 ? 2 : 1;
+                           : N == 6 ? 5 : N == 7 ? 1 : N == 8 ? 3 : N == 9 ? 1 : N == 10 ? 2 : 1;
   static constexpr int THREADS = ((EPB * NP2 + 63) / 64) * 64;
   static constexpr int NPAD = NP | 1;  // odd row stride: conflict-free column reads
 };
@@ -169,14 +169,26 @@ __global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, 
   const int64_t e = a.e0 + el_local;
 
   const SEM_GLOBAL T* Dgl = gl(Dg);
-  T Dr[NP], Ds[NP], DrT[NP], DsT[NP];
+  // FP64 at N >= 8: the four per-lane rows of Dhat would take 8 NP registers
+  // and leave one wave per SIMD; they are read from LDS instead
+  constexpr bool DLDS = sizeof(T) == 8 && N >= 8;
+  __shared__ T s_D[DLDS ? NP2 : 1];
+  T Dr[DLDS ? 1 : NP], Ds[DLDS ? 1 : NP], DrT[DLDS ? 1 : NP], DsT[DLDS ? 1 : NP];
+  if constexpr (DLDS) {
+    for (int t = tid; t < NP2; t += C::THREADS) s_D[t] = Dgl[t];
+  } else {
 #pragma unroll
-  for (int q = 0; q < NP; ++q) {
-    Dr[q] = Dgl[i * NP + q];
-    Ds[q] = Dgl[j * NP + q];
-    DrT[q] = Dgl[q * NP + i];
-    DsT[q] = Dgl[q * NP + j];
+    for (int q = 0; q < NP; ++q) {
+      Dr[q] = Dgl[i * NP + q];
+      Ds[q] = Dgl[j * NP + q];
+      DrT[q] = Dgl[q * NP + i];
+      DsT[q] = Dgl[q * NP + j];
+    }
   }
+  auto dr = [&](int q) -> T { if constexpr (DLDS) return s_D[i * NP + q]; else return Dr[q]; };
+  auto ds = [&](int q) -> T { if constexpr (DLDS) return s_D[j * NP + q]; else return Ds[q]; };
+  auto drt = [&](int q) -> T { if constexpr (DLDS) return s_D[q * NP + i]; else return DrT[q]; };
+  auto dst = [&](int q) -> T { if constexpr (DLDS) return s_D[q * NP + j]; else return DsT[q]; };
 
   // issue every load of the column up front: u (NP values) and the six
   // geometric factors (6 NP values), so a wave has its whole element in flight
@@ -203,8 +215,8 @@ __global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, 
       T ur = 0, us = 0, ut = 0;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        ur += Dr[q] * s_u[elc][k][j][q];
-        us += Ds[q] * s_u[elc][k][q][i];
+        ur += dr(q) * s_u[elc][k][j][q];
+        us += ds(q) * s_u[elc][k][q][i];
         ut += Dgl[k * NP + q] * uk[q];
       }
       const T grr = gk[0][k], grs = gk[1][k], grt = gk[2][k];
@@ -230,8 +242,8 @@ __global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, 
       T au = 0;
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        au += DrT[q] * s_wr[elc][k][j][q];
-        au += DsT[q] * s_ws[elc][k][q][i];
+        au += drt(q) * s_wr[elc][k][j][q];
+        au += dst(q) * s_ws[elc][k][q][i];
         au += Dgl[q * NP + k] * wt[q];
       }
       if constexpr (HELM) au += bk[k] * uk[k];
