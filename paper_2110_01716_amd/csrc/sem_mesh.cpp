@@ -363,9 +363,10 @@ extern "C" int sem_mesh_create(const sem_mesh_desc* d, sem_mesh* out) {
     if (d->E < 1) fail(SEM_EINVAL, "sem_mesh_create: E=%lld < 1", (long long)d->E);
     if (!d->x || !d->y || !d->z || !d->gid) fail(SEM_EINVAL, "sem_mesh_create: NULL coordinate or gid array");
     const int64_t Np = (int64_t)(d->N + 1) * (d->N + 1) * (d->N + 1);
+    if (d->E > 2147483647LL / Np)
+      fail(SEM_EINVAL, "sem_mesh_create: %lld elements of %lld points exceed 2^31-1 local points", (long long)d->E,
+           (long long)Np);
     const int64_t nloc = d->E * Np;
-    if (nloc > 2147483647LL)
-      fail(SEM_EINVAL, "sem_mesh_create: %lld local points exceed 2^31-1", (long long)nloc);
     for (int64_t l = 0; l < nloc; ++l)
       if (d->gid[l] < 0)
         fail(SEM_EINVAL, "sem_mesh_create: negative global ID at element %lld, point %lld", (long long)(l / Np),

@@ -74,3 +74,14 @@ def test_host_argument_errors(lib):
     assert lib.sem_stream(2, None, None, 1.0, 3, None) == sem.SEM_EINVAL
     assert lib.sem_stream(2, None, None, 1.0, 0, None) == sem.SEM_OK
     assert lib.sem_dot_noalloc(None, 0, None, None, None, None) == sem.SEM_EINVAL
+    # mesh sizes: rejected before any array is read or any device call is made,
+    # including element counts whose point count would overflow 64 bits
+    import ctypes as C
+    h = C.c_void_p()
+    dummy = C.c_double(0.0)
+    for N, E in ((0, 1), (16, 1), (7, 0), (7, 2 ** 22), (1, 2 ** 61)):
+        d = sem.sem_mesh_desc(N=N, E=E, x=C.addressof(dummy), y=C.addressof(dummy), z=C.addressof(dummy),
+                              gid=C.addressof(dummy))
+        assert lib.sem_mesh_create(C.byref(d), C.byref(h)) == sem.SEM_EINVAL
+        assert h.value is None
+    assert b"2^31-1" in lib.sem_last_error()
