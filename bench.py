@@ -373,15 +373,19 @@ def bench_batched(sem, count=256, sequential=True):
     out = {"problems": count, "local_points": npts, "setup_s": round(setup, 2), "batched_s": round(tb, 4),
            "batched_solves_per_s": round(count / tb, 1), "status_ok": all(i["status"] == 0 for i in infos),
            "max_relres_true": max(i["relres_true"] for i in infos),
-           "iters_mean": float(np.mean([i["iters"] for i in infos])), "iters_max": max(i["iters"] for i in infos)}
+           "iters_mean": float(np.mean([i["iters"] for i in infos])), "iters_max": max(i["iters"] for i in infos),
+           # one launch per phase over all unfinished problems; the last problem to finish reports the whole call
+           "kernel_launches": max(i["launches"] for i in infos)}
     if sequential:
         xs = [torch.empty_like(b) for b in bs]
+        launches = 0
         t = time.perf_counter()
         for m, p, b, x in zip(meshes, pmgs, bs, xs):
-            sem.sem_pcg_solve(m.h, p.h, b, x, opts)
+            launches += sem.sem_pcg_solve(m.h, p.h, b, x, opts)["launches"]
         torch.cuda.synchronize()
         ts = time.perf_counter() - t
         out["sequential_s"] = round(ts, 4)
+        out["sequential_kernel_launches"] = launches
         out["speedup_batched_vs_sequential"] = round(ts / tb, 2)
         out["bitwise_equal_to_alone"] = all(torch.equal(a, b) for a, b in zip(xs, xb))
     for p in pmgs:

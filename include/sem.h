@@ -266,6 +266,13 @@ typedef struct {
   double seconds;             /* wall time of the solve call                    */
   double relres_initial;      /* ||b - A x0|| / ||b|| of the starting guess: 1
                                  for x0 = 0, smaller after projection           */
+  int64_t launches;           /* kernels queued for the solve from its start to
+                                 its completion, one per phase of an iteration;
+                                 in a batched or continuous-batching call the
+                                 launches are shared by the problems in flight,
+                                 so the last problem to finish reports the
+                                 whole call. Projected solves report their
+                                 inner solve's; GMRES reports 0 (not counted) */
 } sem_solve_info;
 
 /* Solves A x = b, A the assembled masked SEM Laplacian, with Jacobi-PCG

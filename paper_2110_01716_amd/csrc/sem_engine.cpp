@@ -101,6 +101,7 @@ struct Slot {
   int64_t stride = 0;
   int idx = -1;
   int state = 0;  // 0 free, 1 admitted, 2 running, 3 finished
+  int64_t launches0 = 0;  // the batch's launch count when this solve was admitted
   Clock::time_point t0;
   sem_solve_info info{};
   double* scal[2] = {nullptr, nullptr};  // device: outer, coarse
@@ -916,6 +917,7 @@ struct sem_batch_s {
   std::unique_ptr<sem::Plan> plan;
   bool dirty = true;
   sem_probe probe_outer, probe_coarse;  // separate channels: a coarse loop runs while an outer probe is pending
+  int64_t launches = 0;                 // kernels queued through plans so far
 
   size_t scal_bytes() const { return sizeof(double) * 2 * sem::S_COUNT * max_slots; }
   size_t flag_bytes() const { return sizeof(int) * 2 * sem::F_COUNT * max_slots; }
@@ -985,8 +987,10 @@ static const int* probe_flags(const int* block, int k, int stage) {
   return block + (size_t)2 * F_COUNT * k + (size_t)stage * F_COUNT;
 }
 
-static void run(const std::vector<Fn>& seq, hipStream_t s) {
-  for (const Fn& f : seq) f(s);
+// queues one plan sequence (one kernel per entry) and counts its launches
+static void run(sem_batch_s* B, const std::vector<Fn>& seq) {
+  for (const Fn& f : seq) f(B->stream);
+  B->launches += (int64_t)seq.size();
 }
 
 // one pass of every group's body. The coarse loop is queued in chunks; after
@@ -995,14 +999,14 @@ static void run(const std::vector<Fn>& seq, hipStream_t s) {
 // finished runs as no-ops: its launches skip finished problems).
 static void run_body(sem_batch_s* B, Plan& P) {
   for (Group& g : P.groups) {
-    run(g.head, B->stream);
+    run(B, g.head);
     if (!g.cinit.empty()) {
-      run(g.cinit, B->stream);
+      run(B, g.cinit);
       sem_probe& pr = B->probe_coarse;
       int ran = 0;
       while (ran < g.coarse_limit) {
         const int chunk = g.coarse_fixed > 0 ? g.coarse_limit : std::min(g.coarse_check, g.coarse_limit - ran);
-        for (int k = 0; k < chunk; ++k) run(g.citer, B->stream);
+        for (int k = 0; k < chunk; ++k) run(B, g.citer);
         ran += chunk;
         if (pr.pending) {
           const int* fl = probe_wait(pr);
@@ -1016,7 +1020,7 @@ static void run_body(sem_batch_s* B, Plan& P) {
       }
       if (pr.pending) (void)probe_wait(pr);
     }
-    run(g.tail, B->stream);
+    run(B, g.tail);
   }
 }
 
@@ -1051,6 +1055,7 @@ static void batch_add(sem_batch_s* B, sem_mesh m, sem_pmg p, const double* b, do
   s.info.status = 1;
   s.info.relres_initial = 1.0;  // x0 = 0
   s.t0 = Clock::now();
+  s.launches0 = B->launches;
   SEM_HIP(hipMemsetAsync(s.scal[0], 0, sizeof(double) * 2 * S_COUNT, B->stream));
   SEM_HIP(hipMemsetAsync(s.flags[0], 0, sizeof(int) * 2 * F_COUNT, B->stream));
   B->dirty = true;
@@ -1098,7 +1103,7 @@ static void finish_slots(sem_batch_s* B, const std::vector<Slot*>& S) {
     }, 0);
     P.fin(seq, need, FIN_STORE, 0, [](Slot& s) { return vec_blocks(s.level(0).nloc); }, 0);
     P.upload(B->stream);
-    run(seq, B->stream);
+    run(B, seq);
     fetch_ctrl(B);  // also waits before P's tables are freed
     for (Slot* s : need)
       s->info.relres_true = std::sqrt(host_scal(B, s->idx, 0)[S_TMP] / host_scal(B, s->idx, 0)[S_BB]);
@@ -1106,6 +1111,7 @@ static void finish_slots(sem_batch_s* B, const std::vector<Slot*>& S) {
   const auto now = Clock::now();
   for (Slot* s : S) {
     s->info.seconds = std::chrono::duration<double>(now - s->t0).count();
+    s->info.launches = B->launches - s->launches0;
     s->state = 3;
   }
 }
@@ -1117,7 +1123,7 @@ static int batch_step(sem_batch_s* B, int iters) {
     if (s.state == 1) fresh.push_back(&s);
   if (!fresh.empty()) {
     auto P = make_plan(fresh, true, false, B->stream);
-    for (Group& g : P->groups) run(g.init, B->stream);
+    for (Group& g : P->groups) run(B, g.init);
     SEM_HIP(hipStreamSynchronize(B->stream));
     for (Slot* s : fresh) s->state = 2;
     B->dirty = true;

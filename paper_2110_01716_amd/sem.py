@@ -65,7 +65,7 @@ class sem_solve_opts(C.Structure):
 class sem_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double),
                 ("relres_true", C.c_double), ("coarse_iters", C.c_int64), ("seconds", C.c_double),
-                ("relres_initial", C.c_double)]
+                ("relres_initial", C.c_double), ("launches", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -283,6 +283,12 @@ def test_batched_equals_alone_bitwise(sem):
     for a, bi, xa, xb in zip(alone, infos, xs_alone, xs_batch):
         assert a["iters"] == bi["iters"]
         assert torch.equal(xa, xb)
+    # launch counts: every solve queues kernels; the batched call shares one
+    # launch per phase among the problems in flight, so it queues fewer than
+    # the solves one by one, and no problem finishes after the whole call
+    assert all(a["launches"] > 0 for a in alone) and all(i["launches"] > 0 for i in infos)
+    total = max(i["launches"] for i in infos)
+    assert max(a["launches"] for a in alone) <= total < sum(a["launches"] for a in alone)
 
 
 def test_batched_solutions_match_oracle(sem):
