@@ -102,6 +102,7 @@ struct Slot {
   int idx = -1;
   int state = 0;  // 0 free, 1 admitted, 2 running, 3 finished
   int64_t launches0 = 0;  // the batch's launch count when this solve was admitted
+  bool ctrl_clean = false;  // its scalars and flags are still zero from the batch's initialisation
   Clock::time_point t0;
   sem_solve_info info{};
   double* scal[2] = {nullptr, nullptr};  // device: outer, coarse
@@ -955,6 +956,7 @@ static void batch_init(sem_batch_s* B, int max_slots, hipStream_t s) {
     sl.scal[1] = sc + S_COUNT;
     sl.flags[0] = fl;
     sl.flags[1] = fl + F_COUNT;
+    sl.ctrl_clean = true;  // cleared above
   }
 }
 
@@ -1056,8 +1058,11 @@ static void batch_add(sem_batch_s* B, sem_mesh m, sem_pmg p, const double* b, do
   s.info.relres_initial = 1.0;  // x0 = 0
   s.t0 = Clock::now();
   s.launches0 = B->launches;
-  SEM_HIP(hipMemsetAsync(s.scal[0], 0, sizeof(double) * 2 * S_COUNT, B->stream));
-  SEM_HIP(hipMemsetAsync(s.flags[0], 0, sizeof(int) * 2 * F_COUNT, B->stream));
+  if (!s.ctrl_clean) {  // a reused slot: clear what the previous solve left
+    SEM_HIP(hipMemsetAsync(s.scal[0], 0, sizeof(double) * 2 * S_COUNT, B->stream));
+    SEM_HIP(hipMemsetAsync(s.flags[0], 0, sizeof(int) * 2 * F_COUNT, B->stream));
+  }
+  s.ctrl_clean = false;
   B->dirty = true;
   if (slot_out) *slot_out = k;
 }
