@@ -40,16 +40,21 @@ using Fn = std::function<void(hipStream_t)>;
 using Clock = std::chrono::steady_clock;
 
 // ---------------------------------------------------------------------------
-// workspace pool: reuse freed solve workspaces (no allocation on the hot path)
+// workspace pool: reuse freed solve workspaces (no allocation on the hot path).
+// Blocks are kept per device: a block is handed out again only on the device
+// it was allocated on (the device current at pool_get).
 // ---------------------------------------------------------------------------
 static std::mutex g_pool_mu;
-static std::multimap<size_t, void*> g_pool;
+static std::multimap<std::pair<int, size_t>, void*> g_pool;  // (device, bytes) -> free block
+static std::map<void*, int> g_pool_dev;                      // device of every block the pool allocated
 
 void* pool_get(size_t bytes) {
+  int dev = 0;
+  SEM_HIP(hipGetDevice(&dev));
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    auto it = g_pool.lower_bound(bytes);
-    if (it != g_pool.end() && it->first <= bytes + bytes / 8) {
+    auto it = g_pool.lower_bound({dev, bytes});
+    if (it != g_pool.end() && it->first.first == dev && it->first.second <= bytes + bytes / 8) {
       void* p = it->second;
       g_pool.erase(it);
       return p;
@@ -59,9 +64,13 @@ void* pool_get(size_t bytes) {
   hipError_t e = hipMalloc(&p, bytes);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
+    // give this device's free blocks back and try once more
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    for (auto& kv : g_pool) (void)hipFree(kv.second);
-    g_pool.clear();
+    for (auto it = g_pool.lower_bound({dev, 0}); it != g_pool.end() && it->first.first == dev;) {
+      (void)hipFree(it->second);
+      g_pool_dev.erase(it->second);
+      it = g_pool.erase(it);
+    }
     e = hipMalloc(&p, bytes);
   }
   if (e != hipSuccess) {
@@ -69,13 +78,17 @@ void* pool_get(size_t bytes) {
     fail(e == hipErrorOutOfMemory ? SEM_ENOMEM : SEM_EHIP, "workspace allocation of %zu bytes failed: %s", bytes,
          hipGetErrorString(e));
   }
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pool_dev[p] = dev;
   return p;
 }
 
 void pool_put(void* p, size_t bytes) {
   if (!p) return;
   std::lock_guard<std::mutex> lk(g_pool_mu);
-  g_pool.emplace(bytes, p);
+  auto d = g_pool_dev.find(p);
+  if (d == g_pool_dev.end()) return;  // not a pool block
+  g_pool.emplace(std::make_pair(d->second, bytes), p);
 }
 
 // ---------------------------------------------------------------------------
@@ -865,10 +878,12 @@ void Plan::build_init(Group& g) {
 static std::string signature(const Slot& s) {
   if (!s.pmg) return s.lam() != 0.0 ? "jacobi-helmholtz" : "jacobi";
   const sem_pmg_opts& o = s.pmg->o;
-  char buf[128];
-  snprintf(buf, sizeof(buf), "pmg L%d t%d k%d pre%d post%d cf%d cm%d cc%d sm%d", s.pmg->n_levels,
+  // every option a group reads from its first problem (the per-level data,
+  // rho and the Chebyshev coefficients, are read per problem)
+  char buf[160];
+  snprintf(buf, sizeof(buf), "pmg L%d t%d k%d pre%d post%d cf%d cm%d cc%d sm%d cr%.17g", s.pmg->n_levels,
            (int)o.smoother_dtype, o.cheb_degree, o.pre, o.post, o.coarse_fixed_iters, o.coarse_maxit,
-           o.coarse_check_every, o.smoother);
+           o.coarse_check_every, o.smoother, o.coarse_rtol);
   return buf;
 }
 

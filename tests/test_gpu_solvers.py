@@ -291,6 +291,29 @@ def test_batched_equals_alone_bitwise(sem):
     assert max(a["launches"] for a in alone) <= total < sum(a["launches"] for a in alone)
 
 
+def test_batched_mixed_coarse_tolerances_equal_alone(sem):
+    """Hierarchies with different coarse tolerances in one batched call: each
+    problem is solved with its own (bitwise equal to its solve alone)."""
+    import torch
+    print_case("batched-coarse-rtol")
+    bm = wl.box_mesh(3, N=5, deform=0.05, seed=1007)
+    m = sem.Mesh.from_box(bm)
+    pa, pb = sem.Pmg(m, coarse_rtol=1e-2), sem.Pmg(m, coarse_rtol=1e-6)
+    b = dev(wl.random_rhs(bm, 2007))
+    o = sem.solve_opts(rtol=1e-8)
+    xa, xb = torch.empty_like(b), torch.empty_like(b)
+    ia = sem.sem_pcg_solve(m.h, pa.h, b, xa, o)
+    ib = sem.sem_pcg_solve(m.h, pb.h, b, xb, o)
+    assert ia["coarse_iters"] != ib["coarse_iters"]  # the tolerances do differ in effect
+    ya, yb = torch.empty_like(b), torch.empty_like(b)
+    rc, infos = sem.sem_pcg_solve_batched([m.h, m.h], [pa.h, pb.h], [b, b], [ya, yb], o)
+    assert rc == 0
+    assert [i["coarse_iters"] for i in infos] == [ia["coarse_iters"], ib["coarse_iters"]]
+    assert torch.equal(ya, xa) and torch.equal(yb, xb)
+    pa.close()
+    pb.close()
+
+
 def test_batched_solutions_match_oracle(sem):
     """The batched configuration's problem mix (N = 5, 7 and 9, hierarchies
     5->2->1, 7->3->1, 9->4->1, deformed boxes of different sizes) solved in
