@@ -47,3 +47,36 @@ def test_dot_noalloc_matches_dot(sem, dtype):
         assert got == sem.sem_dot_noalloc(m.h, u, v)  # deterministic
     for m, *_ in cases[:2]:
         m.close()
+
+
+def test_dot_noalloc_size_limit(sem):
+    """At the stated maximum (2^27 local points: the 64^3 N=7 mesh) the result
+    matches sem_dot; one more layer of elements is refused with a clear error,
+    and the entry point works again afterwards."""
+    import torch
+    print_case("dot-noalloc-limit")
+    bm = wl.box_mesh(64, N=7)
+    assert bm.E * bm.Np == 2 ** 27
+    m = sem.Mesh.from_box(bm)
+    del bm
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    u = torch.rand((64 ** 3, 512), dtype=torch.float64, device="cuda", generator=g)
+    v = torch.rand((64 ** 3, 512), dtype=torch.float64, device="cuda", generator=g)
+    ref = sem.sem_dot(m.h, u, v)
+    got = sem.sem_dot_noalloc(m.h, u, v)
+    assert abs(got - ref) <= 1e-13 * ref
+    m.close()
+    del u, v
+    bm = wl.box_mesh(64, 64, 65, N=7)
+    m = sem.Mesh.from_box(bm)
+    del bm
+    u = torch.zeros((64 * 64 * 65, 512), dtype=torch.float64, device="cuda")
+    with pytest.raises(sem.SemError, match="static scratch"):
+        sem.sem_dot_noalloc(m.h, u, u)
+    m.close()
+    del u
+    small = wl.box_mesh(2, N=3, deform=0.05, seed=9)
+    ms, us, vs, ref, scale = _case(sem, small, 51, torch.float64)
+    assert abs(sem.sem_dot_noalloc(ms.h, us, vs) - ref) <= 1e-13 * scale
+    ms.close()
