@@ -100,9 +100,32 @@ def build(jobs: int | None = None, debug: bool = False, verbose: bool = True) ->
     return LIB
 
 
+SAN_DIGEST = os.path.join(BUILD_SAN, "sources.sha256")
+
+
+def san_sources_digest() -> str:
+    """SHA-256 over the sources the sanitized build compiles (library sources,
+    the public header, the driver), by content: a checkout that only touches
+    modification times leaves it unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(PKG, "csrc")
+    files = [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))]
+    files += [os.path.join(ROOT, "include", "sem.h"), DRIVER_SAN]
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build_sanitized(jobs: int | None = None, verbose: bool = True) -> str:
-    """Host-ASan/UBSan copy of the library plus the driver that exercises it."""
+    """Host-ASan/UBSan copy of the library plus the driver that exercises it;
+    records the digest of the sources it was built from."""
     os.makedirs(BUILD_SAN, exist_ok=True)
+    if os.path.exists(SAN_DIGEST):
+        os.remove(SAN_DIGEST)
+    digest = san_sources_digest()
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     objs = []
@@ -125,6 +148,10 @@ def build_sanitized(jobs: int | None = None, verbose: bool = True) -> str:
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"sanitized build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if san_sources_digest() != digest:
+        raise RuntimeError("sanitized build: the sources changed while they were compiled; build again")
+    with open(SAN_DIGEST, "w") as fh:
+        fh.write(digest + "\n")
     if verbose:
         print(f"  linked {lib} and {os.path.join(BUILD_SAN, 'sem_sanitize_driver')}", flush=True)
     return lib

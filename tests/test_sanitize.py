@@ -7,34 +7,30 @@ instrumented (a planted heap overflow in its own host code is reported); the
 GPU test runs the driver over the C ABI: mesh setup (gather-scatter map), pMG
 setup (coarse entity keys), Schwarz setup (face maps), solves, batches,
 projection, GMRES and the error paths. Both skip when the sanitized build is
-absent or older than the sources it was built from.
+absent or was built from sources whose contents have changed since (the build
+records a digest of them).
 """
 import os
 import subprocess
 
 import pytest
 
+from paper_2110_01716_amd import build_lib
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SAN = os.path.join(ROOT, "paper_2110_01716_amd", "_build_san")
+SAN = build_lib.BUILD_SAN
 DRIVER = os.path.join(SAN, "sem_sanitize_driver")
-LIB_SOURCES = [os.path.join(ROOT, "paper_2110_01716_amd", "csrc", f)
-               for f in os.listdir(os.path.join(ROOT, "paper_2110_01716_amd", "csrc"))] + \
-              [os.path.join(ROOT, "include", "sem.h")]
-DRIVER_SOURCE = os.path.join(ROOT, "tests", "sanitize", "sem_sanitize_driver.cpp")
 ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:protect_shadow_gap=0", UBSAN_OPTIONS="print_stacktrace=1")
 
 
 def _built():
-    if not os.path.exists(DRIVER):
+    if not os.path.exists(DRIVER) or not os.path.exists(os.path.join(SAN, "libsem_san.so")):
         return "sanitized build absent (python -m paper_2110_01716_amd.build_lib --sanitize)"
-    lib = os.path.join(SAN, "libsem_san.so")
-    if not os.path.exists(lib):
-        return "sanitized library absent"
-    stale = [f for f in LIB_SOURCES if os.path.getmtime(f) > os.path.getmtime(lib)]
-    if os.path.getmtime(DRIVER_SOURCE) > os.path.getmtime(DRIVER):
-        stale.append(DRIVER_SOURCE)
-    if stale:
-        return f"sanitized build older than {os.path.basename(stale[0])}"
+    if not os.path.exists(build_lib.SAN_DIGEST):
+        return "sanitized build has no source digest (build it again)"
+    with open(build_lib.SAN_DIGEST) as fh:
+        if fh.read().strip() != build_lib.san_sources_digest():
+            return "sanitized build is older than its sources (their contents changed since)"
     return None
 
 
