@@ -104,14 +104,15 @@ SAN_DIGEST = os.path.join(BUILD_SAN, "sources.sha256")
 
 
 def san_sources_digest() -> str:
-    """SHA-256 over the sources the sanitized build compiles (library sources,
-    the public header, the driver), by content: a checkout that only touches
-    modification times leaves it unchanged."""
+    """SHA-256 over what the sanitized build is made from (library sources,
+    the public header, the driver, this build script with its flags), by
+    content: a checkout that only touches modification times leaves it
+    unchanged."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(PKG, "csrc")
     files = [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))]
-    files += [os.path.join(ROOT, "include", "sem.h"), DRIVER_SAN]
+    files += [os.path.join(ROOT, "include", "sem.h"), DRIVER_SAN, os.path.abspath(__file__)]
     for f in files:
         h.update(os.path.relpath(f, ROOT).encode())
         with open(f, "rb") as fh:
