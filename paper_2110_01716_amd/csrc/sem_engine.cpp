@@ -173,7 +173,8 @@ size_t layout(Slot& s, uint8_t* base) {
     if (c.assembled) {
       s.cz = (double*)take(8 * nc);
       s.clocal = (double*)take(8 * c.nloc);
-      stride = std::max<int64_t>(stride, std::max<int64_t>(spmv_blocks(nc), vec_blocks(nc)));
+      stride = std::max<int64_t>(stride, std::max<int64_t>(std::max<int64_t>(spmv_blocks(nc), cg_update_blocks(nc)),
+                                                          vec_blocks(nc)));
     } else {
       stride = std::max<int64_t>(stride, std::max<int64_t>(ax_blocks(c.N, c.E), vec_blocks(c.nloc)));
     }
@@ -505,7 +506,7 @@ class Plan {
       a.partial = s->partial;
       a.stride = s->stride;
       a.nblk_upd = cg_update_blocks(a.n);
-      a.nblk_sp = spmv_blocks(a.n);
+      a.nblk_sp = cg_update_blocks(a.n);  // the SpMV launch runs on the same grid as the update
       a.scal = s->scal[1];
       a.flags = s->flags[1];
       a.total = s->flags[0] + F_TOTAL;
