@@ -239,6 +239,7 @@ def solve_pair(sem, bm, m, label, skip_pcg=False, samples=None, smoothers=True, 
         sem.sem_gmres_solve(m.h, p.h, 6, b, x, o8)  # warm
         out["pmg_fp32_gmres6"] = timed_solve(sem, m, p, b, x, o8, gmres_K=6)
         log(label, "pmg-gmres6", out["pmg_fp32_gmres6"])
+        ras = None
         for sm in ("asm", "ras"):
             t = time.time()
             ps = sem.Pmg(m, smoother=sm)
@@ -248,7 +249,10 @@ def solve_pair(sem, bm, m, label, skip_pcg=False, samples=None, smoothers=True, 
             rec.update({"setup_s": round(setup_s, 2), "rho": ps.info()["rho"][:2]})
             out[f"pmg_fp32_cheb_{sm}"] = rec
             log(label, f"pmg-{sm}", rec)
-            ps.close()
+            if sm == "ras":
+                ras = ps  # kept for its time to the target error below
+            else:
+                ps.close()
     xref, out["reference"] = reference_solution(sem, m, b, samples)
     log(label, "reference", out["reference"])
     out["pmg_fp32"].update(solution_errors(xp, samples, xref))
@@ -258,6 +262,10 @@ def solve_pair(sem, bm, m, label, skip_pcg=False, samples=None, smoothers=True, 
                                  "oracle_relres_true": samples["meta"].get("relres_true")}
     tte = {"pmg_fp32": time_to_error(sem, m, p, b, x, samples, xref, rtols)}
     log(label, "pmg time-to-error", tte["pmg_fp32"])
+    if smoothers and ras is not None:
+        tte["pmg_fp32_cheb_ras"] = time_to_error(sem, m, ras, b, x, samples, xref, rtols)
+        log(label, "pmg-ras time-to-error", tte["pmg_fp32_cheb_ras"])
+        ras.close()
     if not skip_pcg:
         xw = torch.empty_like(b)
         sem.sem_pcg_solve(m.h, None, b, xw, sem.solve_opts(maxit=3), check=False)  # workspace
@@ -270,6 +278,10 @@ def solve_pair(sem, bm, m, label, skip_pcg=False, samples=None, smoothers=True, 
         if tte["pmg_fp32"]["to_target"] and tte["pcg_fp64"]["to_target"]:
             tte["speedup_pmg_vs_pcg_at_equal_error"] = round(
                 tte["pcg_fp64"]["to_target"]["seconds"] / tte["pmg_fp32"]["to_target"]["seconds"], 2)
+        ras_hit = tte.get("pmg_fp32_cheb_ras", {}).get("to_target")
+        if ras_hit and tte["pcg_fp64"]["to_target"]:
+            tte["speedup_pmg_ras_vs_pcg_at_equal_error"] = round(
+                tte["pcg_fp64"]["to_target"]["seconds"] / ras_hit["seconds"], 2)
         del xw
     out["time_to_1e-8_solution_error"] = tte
     p.close()
