@@ -51,7 +51,7 @@ typedef enum {
   SEM_OK = 0,
   SEM_EINVAL = -1,   /* bad argument, shape or inconsistent mesh data        */
   SEM_EGEOM = -2,    /* Jacobian determinant <= 0 at some GLL point           */
-  SEM_ENOMEM = -3,   /* device allocation failed or over the memory budget    */
+  SEM_ENOMEM = -3,   /* device or host allocation failed, or over the budget  */
   SEM_EHIP = -4,     /* a HIP runtime call failed                             */
   SEM_ENOCONV = -5,  /* iteration limit reached; x holds the last iterate     */
   SEM_ENAN = -6,     /* NaN or Inf met in the right-hand side or an iterate   */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <new>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -41,8 +42,14 @@ int guarded(F&& f) {
     return SEM_OK;
   } catch (const Error& e) {
     return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host memory exhausted");
+    return SEM_ENOMEM;
   } catch (const std::exception& e) {
     set_error("internal error: %s", e.what());
+    return SEM_EHIP;
+  } catch (...) {  // nothing crosses the C ABI
+    set_error("internal error: unknown exception");
     return SEM_EHIP;
   }
 }

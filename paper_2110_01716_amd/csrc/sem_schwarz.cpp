@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <exception>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -307,9 +308,21 @@ void schwarz_setup(const MeshData& m, bool ras, SchwarzData& sw, hipStream_t s) 
   };
   const int nth = (int)std::max<int64_t>(1, std::min<int64_t>(16, std::min<int64_t>(E / 64 + 1,
                                                        (int64_t)std::thread::hardware_concurrency())));
+  // an exception in a worker (allocation) is carried back and rethrown here,
+  // so it becomes the call's error status instead of ending the process
   std::vector<std::thread> th;
-  for (int t = 0; t < nth; ++t) th.emplace_back(work, E * t / nth, E * (t + 1) / nth);
+  std::vector<std::exception_ptr> err(nth);
+  for (int t = 0; t < nth; ++t)
+    th.emplace_back([&, t] {
+      try {
+        work(E * t / nth, E * (t + 1) / nth);
+      } catch (...) {
+        err[t] = std::current_exception();
+      }
+    });
   for (auto& t : th) t.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
   std::vector<float> S32(S64.begin(), S64.end()), L32(L64.begin(), L64.end());
   sw.S64.alloc(sizeof(double) * S64.size());
   sw.L64.alloc(sizeof(double) * L64.size());
