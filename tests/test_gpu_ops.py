@@ -94,6 +94,9 @@ def test_ax_element_range_leaves_others(sem):
     out = host(Ad)
     assert rel_err(out[5:16], ref[5:16]) <= 1e-12
     assert np.all(out[:5] == 7.0) and np.all(out[16:] == 7.0)
+    # an empty range is a no-op
+    sem.sem_ax(m.h, ud, Ad, e0=3, ne=0)
+    assert np.array_equal(host(Ad), out)
     with pytest.raises(sem.SemError):
         sem.sem_ax(m.h, ud, Ad, e0=20, ne=10)
 
