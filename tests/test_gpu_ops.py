@@ -123,6 +123,22 @@ def test_gather_scatter_and_mask(sem, N):
     np.testing.assert_array_equal(host(one), ops.multiplicity(bm.gid))
 
 
+def test_gather_scatter_nothing_to_do(sem):
+    """One Neumann element has no shared and no Dirichlet nodes: gs launches
+    nothing and leaves the vector as it is, with or without the mask."""
+    import torch
+    print_case("gs-empty")
+    bm = wl.box_mesh(1, N=5, deform=0.05, seed=4, dirichlet=False)
+    m = sem.Mesh.from_box(bm)
+    info = m.info()
+    assert info["n_shared_nodes"] == 0
+    v = np.random.default_rng(8).uniform(-1, 1, bm.x.shape)
+    for mask in (False, True):
+        vd = dev(v)
+        sem.sem_gs(m.h, vd, apply_mask=mask)
+        assert np.array_equal(host(vd), v)
+
+
 def test_gather_scatter_random_relabelling(sem):
     print_case("gs-relabel")
     bm = wl.box_mesh(3, 3, 3, N=4, deform=0.05, seed=2)
