@@ -102,6 +102,39 @@ def time_ax(sem, m, E, Np, steps, warmup, lam=None):
     return wall, ms
 
 
+def bench_ax_orders(sem, steps=20, warmup=5):
+    """Event-timed Ax at the orders of the batched workload's hierarchies
+    (N = 5, 7, 9), FP64 and FP32, each on a deformed box of ~55M local points."""
+    import torch
+    from paper_2110_01716_amd import workloads as wl
+    out = {}
+    for N, n in ((5, 64), (7, 48), (9, 38)):
+        bm = wl.box_mesh(n, N=N, deform=0.05, seed=1001)
+        m = sem.Mesh.from_box(bm)
+        E, Np = bm.E, bm.Np
+        del bm
+        for dt, bpp in ((torch.float64, 64), (torch.float32, 32)):
+            u = torch.rand((E, Np), dtype=dt, device="cuda") * 2 - 1
+            Au = torch.empty_like(u)
+            for _ in range(warmup):
+                sem.sem_ax(m.h, u, Au)
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+            for a_, b_ in ev:
+                a_.record()
+                sem.sem_ax(m.h, u, Au)
+                b_.record()
+            torch.cuda.synchronize()
+            ms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in ev]))
+            gbs = bpp * E * Np / (ms * 1e-3) / 1e9
+            out[f"N{N}_{'f64' if bpp == 64 else 'f32'}"] = {
+                "elements": E, "local_points": E * Np, "bytes_per_point": bpp, "ms_mean": round(ms, 4),
+                "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "gdofs": round(E * N ** 3 / ms / 1e6, 2)}
+            del u, Au
+        m.close()
+    return out
+
+
 def time_stream(sem, n, steps, warmup):
     """Event-timed bandwidth probe (sem_stream) on n doubles per array: copy
     (16 B per element), STREAM triad (24 B) and the FP64 Ax read:write mix of
@@ -569,6 +602,7 @@ def main():
     ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--solve-only", action="store_true", help="skip the Ax steps (profiling the solve)")
+    ap.add_argument("--ax-orders", action="store_true", help="Ax at N = 5, 7, 9 (FP64 and FP32) only")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration under a profiler)")
     a = ap.parse_args()
@@ -593,6 +627,9 @@ def main():
         del src, dst
     spec = dict(wl.config_meshes()["ax_64x64x64_N7"])
     spec["n"] = a.n
+    if a.ax_orders:
+        print(json.dumps({"ax_orders": bench_ax_orders(sem, a.steps, a.warmup)}), flush=True)
+        return
     if a.batched_only:
         print(json.dumps({"batched": bench_batched(sem)}), flush=True)
         return
