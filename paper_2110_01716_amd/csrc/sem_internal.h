@@ -401,7 +401,7 @@ struct LincombArgs {
 // ---------------------------------------------------------------------------
 // launchers (defined in sem_kernels.hip)
 // ---------------------------------------------------------------------------
-int ax_blocks(int N, int64_t ne);
+int ax_blocks(int N, int64_t ne, bool f32 = false);  // f32: blocks of the FP32 kernel
 int64_t vec_blocks(int64_t n);
 int64_t gs_blocks(int64_t n_shared, int64_t n_dir);
 int xfer_blocks(int Nf, int Nc, int64_t E);

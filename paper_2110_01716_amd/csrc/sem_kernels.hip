@@ -136,19 +136,26 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 // ---------------------------------------------------------------------------
 // Ax
 // ---------------------------------------------------------------------------
-template <int N>
+// elements per block, by order and precision (measured; at N = 5 one FP32
+// element per wave streams 10% faster than seven per block, FP64 the reverse)
+template <typename T>
+constexpr int ax_epb(int N) {
+  return N == 1 ? 64 : N == 2 ? 28 : N == 3 ? 16 : N == 4 ? 10 : N == 5 ? (sizeof(T) == 4 ? 1 : 7)
+       : N == 6 ? 5 : N == 7 ? 1 : N == 8 ? 3 : N == 9 ? 1 : N == 10 ? 2 : 1;
+}
+
+template <int N, typename T>
 struct AxCfg {
   static constexpr int NP = N + 1, NP2 = NP * NP, NP3 = NP2 * NP;
-  static constexpr int EPB = N == 1 ? 64 : N == 2 ? 28 : N == 3 ? 16 : N == 4 ? 10 : N == 5 ? 7
-                           : N == 6 ? 5 : N == 7 ? 1 : N == 8 ? 3 : N == 9 ? 1 : N == 10 ? 2 : 1;
+  static constexpr int EPB = ax_epb<T>(N);
   static constexpr int THREADS = ((EPB * NP2 + 63) / 64) * 64;
   static constexpr int NPAD = NP | 1;  // odd row stride: conflict-free column reads
 };
 
 // ax-kernel-begin
 template <int N, typename T, bool HELM>
-__global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, const T* __restrict__ Dg) {
-  using C = AxCfg<N>;
+__global__ __launch_bounds__((AxCfg<N, T>::THREADS)) void k_ax(Table<AxArgs<T>> tab, const T* __restrict__ Dg) {
+  using C = AxCfg<N, T>;
   constexpr int NP = C::NP, NP2 = C::NP2, NP3 = C::NP3, EPB = C::EPB, NPAD = C::NPAD;
   __shared__ T s_u[EPB][NP][NP][NPAD];
   __shared__ T s_wr[EPB][NP][NP][NPAD];
@@ -259,10 +266,10 @@ __global__ __launch_bounds__(AxCfg<N>::THREADS) void k_ax(Table<AxArgs<T>> tab, 
 
 // ax-kernel-end
 
-int ax_blocks(int N, int64_t ne) {
+int ax_blocks(int N, int64_t ne, bool f32) {
   int epb = 1;
   switch (N) {
-#define SEM_EPB_CASE(n) case n: epb = AxCfg<n>::EPB; break;
+#define SEM_EPB_CASE(n) case n: epb = f32 ? AxCfg<n, float>::EPB : AxCfg<n, double>::EPB; break;
     SEM_EPB_CASE(1) SEM_EPB_CASE(2) SEM_EPB_CASE(3) SEM_EPB_CASE(4) SEM_EPB_CASE(5)
     SEM_EPB_CASE(6) SEM_EPB_CASE(7) SEM_EPB_CASE(8) SEM_EPB_CASE(9) SEM_EPB_CASE(10)
     SEM_EPB_CASE(11) SEM_EPB_CASE(12) SEM_EPB_CASE(13) SEM_EPB_CASE(14) SEM_EPB_CASE(15)
@@ -280,9 +287,9 @@ void launch_ax(int N, const Table<AxArgs<T>>& t, int64_t total_blocks, const T* 
 #define SEM_AX_CASE(n)                                                                        \
   case n:                                                                                     \
     if (helm)                                                                                 \
-      hipLaunchKernelGGL((k_ax<n, T, true>), dim3((unsigned)total_blocks), dim3(AxCfg<n>::THREADS), 0, s, t, D); \
+      hipLaunchKernelGGL((k_ax<n, T, true>), dim3((unsigned)total_blocks), dim3(AxCfg<n, T>::THREADS), 0, s, t, D); \
     else                                                                                      \
-      hipLaunchKernelGGL((k_ax<n, T, false>), dim3((unsigned)total_blocks), dim3(AxCfg<n>::THREADS), 0, s, t, D); \
+      hipLaunchKernelGGL((k_ax<n, T, false>), dim3((unsigned)total_blocks), dim3(AxCfg<n, T>::THREADS), 0, s, t, D); \
     break;
     SEM_AX_CASE(1) SEM_AX_CASE(2) SEM_AX_CASE(3) SEM_AX_CASE(4) SEM_AX_CASE(5)
     SEM_AX_CASE(6) SEM_AX_CASE(7) SEM_AX_CASE(8) SEM_AX_CASE(9) SEM_AX_CASE(10)

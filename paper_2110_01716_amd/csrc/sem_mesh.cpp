@@ -89,7 +89,7 @@ static void ax_range(const MeshData& m, const T* u, T* Au, int64_t e0, int64_t n
   t.one.e0 = e0;
   t.one.ne = ne;
   t.one.partial = partial;
-  launch_ax<T>(m.N, t, ax_blocks(m.N, ne), D_of<T>(m), s);
+  launch_ax<T>(m.N, t, ax_blocks(m.N, ne, sizeof(T) == 4), D_of<T>(m), s);
 }
 
 template <typename T>
