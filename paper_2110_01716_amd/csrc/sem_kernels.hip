@@ -136,12 +136,13 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 // ---------------------------------------------------------------------------
 // Ax
 // ---------------------------------------------------------------------------
-// elements per block, by order and precision (measured; at N = 5 one FP32
-// element per wave streams 10% faster than seven per block; FP64 three per
-// block, 4% faster than seven)
+// elements per block, by order and precision (measured). In FP32 a block
+// that is one wave streams fastest where it fits: at N = 4 two elements (50
+// lanes, 14% faster than ten per block), at N = 5 one (10% faster than seven).
+// In FP64 at N = 5 three elements per block are 4% faster than seven.
 template <typename T>
 constexpr int ax_epb(int N) {
-  return N == 1 ? 64 : N == 2 ? 28 : N == 3 ? 16 : N == 4 ? 10 : N == 5 ? (sizeof(T) == 4 ? 1 : 3)
+  return N == 1 ? 64 : N == 2 ? 28 : N == 3 ? 16 : N == 4 ? (sizeof(T) == 4 ? 2 : 10) : N == 5 ? (sizeof(T) == 4 ? 1 : 3)
        : N == 6 ? 5 : N == 7 ? 1 : N == 8 ? 3 : N == 9 ? 1 : N == 10 ? 2 : 1;
 }
 

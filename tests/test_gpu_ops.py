@@ -67,7 +67,8 @@ def test_ax_fp64(sem, nx, ny, nz, N):
     assert rel_err(host(Ad), ref) <= 1e-12
 
 
-@pytest.mark.parametrize("nx,ny,nz,N", [(3, 3, 3, 7), (2, 3, 5, 3), (3, 4, 5, 1), (2, 2, 3, 9), (2, 3, 3, 5)])
+@pytest.mark.parametrize("nx,ny,nz,N", [(3, 3, 3, 7), (2, 3, 5, 3), (3, 4, 5, 1), (2, 2, 3, 9), (2, 3, 3, 5),
+                                          (3, 2, 3, 4)])
 def test_ax_fp32(sem, nx, ny, nz, N):
     import torch
     print_case("ax32", nx, ny, nz, N)
